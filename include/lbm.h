@@ -1,0 +1,237 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) coupled thermal lattice Boltzmann step.
+ *
+ * Method: the double-distribution-function thermal LB model of Xu, Shi & Xi,
+ * "Lattice Boltzmann simulations of three-dimensional thermal convective flows
+ * at high Rayleigh number", Int. J. Heat Mass Transfer (2019),
+ * arXiv:1903.08882:
+ *   - a D3Q19 MRT lattice for the flow with Guo forcing of the Boussinesq
+ *     buoyancy rho g beta (T - T0) z^ (Sec. 2.2, Eq. MRT);
+ *   - a D3Q7 MRT lattice for the temperature with the relaxation rates that
+ *     make the fourth-order error isotropic (Sec. 2.3, Eq. MRT_T, Eq. magic,
+ *     Eq. 4th, Eq. qnu);
+ *   - half-way bounce-back no-slip walls, half-way anti-bounce-back fixed
+ *     temperature walls and bounce-back adiabatic walls (Sec. 2.2, 2.3);
+ *   - a closed cube: side-heated (Sec. 3) or Rayleigh-Benard (Sec. 4).
+ *
+ * Geometry and units.  N nodes per side, node (i, j, k) at (i+1/2, j+1/2,
+ * k+1/2) lattice units, walls on the planes 0 and N of every axis, cell height
+ * H = N.  Gravity points along -z.  Wall temperatures are T_hot = +1/2 and
+ * T_cold = -1/2 (dT = 1).  Side-heated: hot wall x = 0, cold wall x = N.
+ * Rayleigh-Benard: hot wall z = 0, cold wall z = N.  All other walls are
+ * adiabatic.  Lattice parameters follow from (N, Ra, Pr, U) with the
+ * free-fall scaling of Sec. 2.1: nu = U H sqrt(Pr/Ra), kappa = U H/sqrt(Ra Pr),
+ * g beta = U^2/(H dT).
+ *
+ * Arrays handed across this ABI.  Field and population arrays are FP64,
+ * x fastest: element [q][z][y][x] at q*N^3 + x + N*(y + N*z).  Populations
+ * are q = 0..18 for f_0..f_18 and 19..25 for g_0..g_6, in the velocity order
+ * of the paper's printed arrays, always the pre-collision values of the
+ * current time step.
+ *
+ * Memory and streams.  The caller owns all device memory (one buffer of
+ * lbm_state_bytes() bytes handed to lbm_create) and passes a HIP stream
+ * (hipStream_t as void*, NULL = the default stream) to every call that
+ * launches work.  Calls that return host values synchronise that stream.
+ * Pointers documented as "device" must be device (or managed) memory; the
+ * library never dereferences them on the host.
+ *
+ * Errors.  Every int-returning call returns LBM_OK (0) or a negative code.
+ * lbm_last_error(h) describes the last failure on a handle; no call aborts.
+ * One handle must not be used from two host threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef LBM_API
+#define LBM_API __attribute__((visibility("default")))
+#endif
+
+typedef struct lbm lbm_t; /* opaque handle; owned by the library */
+
+enum lbm_cell { LBM_SIDE_HEATED = 0, LBM_RAYLEIGH_BENARD = 1 };
+
+/* Storage type of the populations in device memory.  Populations are kept as
+ * deviations from the rest equilibrium (f_i - w_i, g_i - w_i^T * 0).
+ * FP64: FP64 storage and arithmetic.  FP32: FP32 storage and arithmetic.
+ * FP16S: FP16 storage of the scaled deviations, FP32 arithmetic. */
+enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 };
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* bad argument (NULL pointer, size, enum)            */
+    LBM_ERANGE = -2,    /* parameters outside the scheme's valid range        */
+    LBM_ENOMEM = -3,    /* caller buffer too small, or allocation failed      */
+    LBM_EDEVICE = -4,   /* HIP runtime error (text in lbm_last_error)         */
+    LBM_EDIVERGED = -5, /* a reduction came back NaN or infinite              */
+    LBM_ESTATE = -6     /* call not valid in the handle's current state       */
+};
+
+/* Raw observables (lattice units, FP64), indices of the LBM_NRAW vector.
+ * Means are over the N^3 nodes, the N^2 nodes of a wall, or the N nodes of a
+ * wall's mid-line (the central y index; mean of the two central indices when
+ * N is even), running along z (side-heated) or x (Rayleigh-Benard).
+ *   FLUX_*: heat entering the fluid through an isothermal wall during the last
+ *           step, per link: (6 + a_T)/21 T_w - 2 g_out, the difference the
+ *           anti-bounce-back rule makes (Sec. 2.3 boundary scheme).
+ *   GRAD_*: -dT/dn into the fluid at the wall, one-sided second-order
+ *           difference (-8 T_w + 9 T_0 - T_1)/3 through the wall point and the
+ *           first two nodes.
+ *   EPS_U:  <nu/2 sum_ij (d_i u_j + d_j u_i)^2>, EPS_T: <kappa |grad T|^2>
+ *           (Sec. 4), central differences inside; at the first node next to a
+ *           wall the quadratic through the wall value (u = 0, T = T_w) and the
+ *           two nearest nodes, -4/3 phi_w + phi_0 + 1/3 phi_1; at an adiabatic
+ *           wall a mirror node (dT/dn = 0): (phi_1 - phi_0)/2.
+ *   DIV2:   <(div u)^2> with the same differences. */
+enum lbm_raw {
+    LBM_RAW_FLUX_HOT = 0, LBM_RAW_FLUX_COLD, LBM_RAW_FLUX_HOT_MID, LBM_RAW_FLUX_COLD_MID,
+    LBM_RAW_GRAD_HOT, LBM_RAW_GRAD_COLD, LBM_RAW_GRAD_HOT_MID, LBM_RAW_GRAD_COLD_MID,
+    LBM_RAW_U2, LBM_RAW_W2, LBM_RAW_WT, LBM_RAW_UT, LBM_RAW_EPS_U, LBM_RAW_EPS_T,
+    LBM_RAW_DRHO2, LBM_RAW_T, LBM_RAW_DRHO, LBM_RAW_DIV2,
+    LBM_NRAW
+};
+
+/* Nondimensional observables (free-fall units u/U, T/dT, lengths in H),
+ * indices of the LBM_NOBS vector filled by lbm_nondimensional().
+ * Nu by link flux: FLUX * H/(kappa dT); Nu by difference: GRAD * H/dT (the
+ * cold wall's sign flipped so both are positive); Nu_vol = 1 + sqrt(Ra Pr)
+ * <w* T*> (Rayleigh-Benard) or <u* T*> (side-heated); Re = sqrt(<|u|^2>) H/nu,
+ * Re_w = sqrt(<w^2>) H/nu; eps_u* = eps_u H/U^3, eps_T* = eps_T H/(U dT^2);
+ * Nu_kin = 1 + sqrt(Ra Pr) eps_u*, Nu_th = sqrt(Ra Pr) eps_T* (Sec. 4);
+ * E = <|u*|^2>/2 (Sec. 3); rms(rho - 1); <T>; rms(div* u*) (Sec. 3). */
+enum lbm_obs {
+    LBM_NU_HOT = 0, LBM_NU_COLD, LBM_NU_HOT_MID, LBM_NU_COLD_MID,
+    LBM_NU_HOT_FD, LBM_NU_COLD_FD, LBM_NU_HOT_MID_FD, LBM_NU_COLD_MID_FD,
+    LBM_RE_RMS, LBM_RE_W, LBM_NU_VOL, LBM_EPS_U, LBM_EPS_T, LBM_NU_KIN, LBM_NU_TH,
+    LBM_E_KIN, LBM_RMS_DRHO, LBM_MEAN_T, LBM_RMS_DIV,
+    LBM_NOBS
+};
+
+typedef struct {
+    double U;         /* free-fall velocity sqrt(g beta dT H) in lattice units;
+                         default 0.1/sqrt(3), i.e. Mach 0.1 (Sec. 3)          */
+    double T0;        /* reference temperature of the buoyancy; default 0    */
+    int sample_every; /* lbm_step adds the observables to the time averages
+                         every this many steps (0 = never; default 0)          */
+    int block;        /* threads per block of the step kernel, a multiple of
+                         64 in [64, 1024]; 0 = library default                */
+} lbm_opts;
+
+/* Lattice parameters derived from (N, Ra, Pr, cell, opts). */
+typedef struct {
+    int N, cell, storage;
+    double Ra, Pr, U, T0, T_hot, T_cold, H, dT;
+    double nu, kappa, gbeta;
+    double tau_f, s_e, s_q;   /* s_e = s_eps = s_nu = s_pi = 1/tau_f; s_q = s_m */
+    double q_k, q_e, q_nu, a_T;
+    double wT0, wT1;          /* D3Q7 weights (1 - a_T)/7 and (6 + a_T)/42     */
+} lbm_params;
+
+/* Fill *o with the defaults above. */
+LBM_API void lbm_default_opts(lbm_opts *o);
+
+/* Host only.  Derive the lattice parameters (Sec. 2.1-2.3):
+ *   tau_f = 3 nu + 1/2, s_q = s_m = 8(2 tau_f - 1)/(8 tau_f - 1),
+ *   q_k = 3 - sqrt 3, q_e = q_nu = 4 sqrt 3 - 6, a_T = 42 sqrt 3 kappa - 6.
+ * opts may be NULL (defaults).  LBM_EINVAL for N < 3, a bad cell or storage,
+ * Ra, Pr or U not positive or not finite; LBM_ERANGE when a_T leaves (-6, 1],
+ * where a D3Q7 weight would turn negative (kappa > 1/(6 sqrt 3)). */
+LBM_API int lbm_derive_params(int N, double Ra, double Pr, int cell, int storage,
+                      const lbm_opts *opts, lbm_params *out);
+
+/* Host only.  Bytes of device memory a handle of size N and storage type
+ * needs (populations, macro planes, residual snapshot, reduction scratch). */
+LBM_API int lbm_state_bytes(int N, int storage, size_t *bytes);
+
+/* Create a handle.  dev_buf: device buffer of at least lbm_state_bytes()
+ * bytes, 256-byte aligned, owned by the caller and kept alive until
+ * lbm_destroy; NULL makes the library allocate (and free) it itself.  The
+ * populations are undefined until lbm_set_fields or lbm_set_populations. */
+LBM_API int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opts *opts,
+               void *dev_buf, size_t buf_bytes, lbm_t **out);
+
+/* Destroy a handle (frees only what the library allocated). */
+LBM_API int lbm_destroy(lbm_t *h);
+
+LBM_API int lbm_get_params(const lbm_t *h, lbm_params *out);
+
+/* Initialise from fields: rho = 1, f = f^eq(1, u) (Sec. 2.2), g = g^eq(T, u)
+ * (Sec. 2.3).  uvwT: device FP64 array [4][N^3] holding u, v, w, T.  Resets
+ * the step counter, the time averages and the residual snapshot. */
+LBM_API int lbm_set_fields(lbm_t *h, const double *uvwT, void *stream);
+
+/* Macroscopic fields of the current state (Sec. 2.2, 2.3):
+ * rho = sum f, T = sum g, u = (sum e f + F/2)/rho with F = rho g beta (T - T0) z^.
+ * out: device FP64 array [5][N^3] receiving rho, u, v, w, T. */
+LBM_API int lbm_get_fields(lbm_t *h, double *out, void *stream);
+
+/* Replace the populations.  in: device FP64 array [26][N^3] of pre-collision
+ * populations.  Keeps the step counter; resets the residual snapshot.  The
+ * values are rounded to the storage type. */
+LBM_API int lbm_set_populations(lbm_t *h, const double *in, void *stream);
+
+/* Pre-collision populations of the current time step.  out: device FP64
+ * array [26][N^3]. */
+LBM_API int lbm_get_populations(lbm_t *h, double *out, void *stream);
+
+/* Advance n >= 0 coupled time steps (Eq. MRT and Eq. MRT_T with the wall
+ * rules), asynchronously on stream.  With opts.sample_every = K > 0 the
+ * observables of every K-th state are added to the time averages. */
+LBM_API int lbm_step(lbm_t *h, int64_t n, void *stream);
+
+/* Steps taken since lbm_set_fields. */
+LBM_API int64_t lbm_time(const lbm_t *h);
+
+/* Raw observables (enum lbm_raw) of the current state; synchronises stream.
+ * The FLUX_* entries refer to the last step taken (zero meaning before the
+ * first step after lbm_set_fields/lbm_set_populations).  LBM_EDIVERGED when
+ * any entry is not finite. */
+LBM_API int lbm_observables_raw(lbm_t *h, void *stream, double raw[LBM_NRAW]);
+
+/* Instantaneous headline observables of the current state, nondimensional:
+ * Nu = mean of the hot- and cold-wall link-flux Nusselt numbers, Re = Re_rms,
+ * eps_u* and eps_T* volume means (Sec. 4).  Any output pointer may be NULL. */
+LBM_API int lbm_observables(lbm_t *h, void *stream, double *Nu, double *Re, double *eps_u,
+                    double *eps_T);
+
+/* Host only.  Convert a raw vector to the LBM_NOBS nondimensional numbers. */
+LBM_API int lbm_nondimensional(const lbm_params *p, const double raw[LBM_NRAW],
+                       double out[LBM_NOBS]);
+
+/* Time averages: the mean raw vector over the states sampled by lbm_step
+ * since the last reset, and the number of samples; synchronises stream.
+ * LBM_ESTATE when no sample was taken yet. */
+LBM_API int lbm_averages(lbm_t *h, void *stream, double raw_mean[LBM_NRAW], int64_t *count);
+LBM_API int lbm_reset_averages(lbm_t *h, void *stream);
+
+/* Steady-state residual against the state recorded at the previous call (or
+ * at initialisation), then record the current state (Sec. 3 criterion):
+ *   max_dT   = max |T - T_old|
+ *   rel_L1_T = sum |T - T_old| / sum |T_old|
+ *   rel_L2_u = sum ||u - u_old||_2 / sum ||u_old||_2
+ * Synchronises stream.  Any output pointer may be NULL. */
+LBM_API int lbm_residual(lbm_t *h, void *stream, double *max_dT, double *rel_L1_T,
+                 double *rel_L2_u);
+
+/* Kernel timing.  With profiling enabled, lbm_step brackets every step
+ * kernel it launches with a pair of HIP events on its stream.
+ * lbm_profile_read synchronises, returns the summed duration (ms) and number
+ * of step kernels timed since the previous read, and starts a new count. */
+LBM_API int lbm_profile(lbm_t *h, int enable);
+LBM_API int lbm_profile_read(lbm_t *h, double *kernel_ms, int64_t *kernels);
+
+LBM_API const char *lbm_last_error(const lbm_t *h);
+LBM_API const char *lbm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -67,6 +67,7 @@ def lib():
         L.orc_fd_derivative.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
         L.orc_fd_derivative.restype = ctypes.c_double
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -102,6 +103,11 @@ def derive(N, Ra, Pr, cell=SIDE_HEATED, U=0.1 / np.sqrt(3.0), T0=0.0):
     if rc != 0:
         raise ValueError(f"orc_derive failed ({rc}) for N={N} Ra={Ra} Pr={Pr} U={U}")
     return p
+
+
+def threads():
+    """OpenMP threads the oracle's whole-lattice loops run on."""
+    return int(lib().orc_threads())
 
 
 def matrix_M():

@@ -33,6 +33,9 @@
  * 0 and N of each axis, so the cell height H equals N.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -40,6 +43,15 @@
 #define Q19 19
 #define Q7 7
 #define NPOP 26
+
+/* Number of OpenMP threads the whole-lattice loops use. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Lattices                                                                 */

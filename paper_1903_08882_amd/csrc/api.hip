@@ -1,0 +1,378 @@
+// api.hip -- host side of the C ABI declared in include/lbm.h: parameter
+// derivation (Sec. 2.1-2.3 of Xu, Shi & Xi 2019), argument checks, the
+// device-memory layout, the step loop and the synchronising queries.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm_internal.h"
+
+namespace {
+
+int fail(lbm_t *h, int code, const char *fmt, const char *a = "") {
+    if (h) {
+        char buf[512];
+        std::snprintf(buf, sizeof buf, fmt, a);
+        h->err = buf;
+    }
+    return code;
+}
+
+int hip_fail(lbm_t *h, hipError_t e, const char *where) {
+    if (h) h->err = std::string(where) + ": " + hipGetErrorString(e);
+    return LBM_EDEVICE;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Copy the result block (doubles [0, count) from res + off) to the host.
+int read_res(lbm_t *h, hipStream_t s, int off, int count, double *dst) {
+    const double *src = reinterpret_cast<const double *>(static_cast<char *>(h->buf) + h->L.off_res) + off;
+    hipError_t e = hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? LBM_OK : hip_fail(h, e, "reading results");
+}
+
+int require_init(lbm_t *h) {
+    if (!h) return LBM_EINVAL;
+    if (!h->initialised) return fail(h, LBM_ESTATE, "populations not set (call lbm_set_fields or lbm_set_populations)");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_default_opts(lbm_opts *o) {
+    if (!o) return;
+    o->U = 0.1 / std::sqrt(3.0);
+    o->T0 = 0.0;
+    o->sample_every = 0;
+    o->block = 0;
+}
+
+int lbm_derive_params(int N, double Ra, double Pr, int cell, int storage, const lbm_opts *opts,
+                      lbm_params *out) {
+    if (!out) return LBM_EINVAL;
+    lbm_opts o;
+    lbm_default_opts(&o);
+    if (opts) o = *opts;
+    std::memset(out, 0, sizeof *out);
+    if (N < 3 || (cell != LBM_SIDE_HEATED && cell != LBM_RAYLEIGH_BENARD) ||
+        (storage != LBM_FP64 && storage != LBM_FP32 && storage != LBM_FP16S) || !finite_pos(Ra) ||
+        !finite_pos(Pr) || !finite_pos(o.U) || !std::isfinite(o.T0) || o.sample_every < 0)
+        return LBM_EINVAL;
+    if (N > lbmk::kMaxN) return LBM_ERANGE;
+    lbm_params &p = *out;
+    p.N = N;
+    p.cell = cell;
+    p.storage = storage;
+    p.Ra = Ra;
+    p.Pr = Pr;
+    p.U = o.U;
+    p.T0 = o.T0;
+    p.T_hot = 0.5;
+    p.T_cold = -0.5;
+    p.H = N;   // node-centred lattice between walls on the planes 0 and N
+    p.dT = p.T_hot - p.T_cold;
+    // free-fall scaling (Sec. 2.1): Ra = g beta dT H^3/(nu kappa), Pr = nu/kappa,
+    // U = sqrt(g beta dT H)
+    p.nu = p.U * p.H * std::sqrt(Pr / Ra);
+    p.kappa = p.U * p.H / std::sqrt(Ra * Pr);
+    p.gbeta = p.U * p.U / (p.H * p.dT);
+    // flow rates (Sec. 2.2): nu = (tau_f - 1/2)/3
+    p.tau_f = 3.0 * p.nu + 0.5;
+    p.s_e = 1.0 / p.tau_f;
+    p.s_q = 8.0 * (2.0 * p.tau_f - 1.0) / (8.0 * p.tau_f - 1.0);
+    // thermal rates for an isotropic fourth-order error (Sec. 2.3)
+    const double r3 = std::sqrt(3.0);
+    p.q_k = 3.0 - r3;
+    p.q_e = 4.0 * r3 - 6.0;
+    p.q_nu = 4.0 * r3 - 6.0;
+    p.a_T = 42.0 * r3 * p.kappa - 6.0;
+    p.wT0 = (1.0 - p.a_T) / 7.0;
+    p.wT1 = (6.0 + p.a_T) / 42.0;
+    if (!(p.a_T > -6.0 && p.a_T <= 1.0)) return LBM_ERANGE;
+    return LBM_OK;
+}
+
+int lbm_state_bytes(int N, int storage, size_t *bytes) {
+    if (!bytes || N < 3 || (storage != LBM_FP64 && storage != LBM_FP32 && storage != LBM_FP16S))
+        return LBM_EINVAL;
+    if (N > lbmk::kMaxN) return LBM_ERANGE;
+    *bytes = lbmk::make_layout(N, storage).total;
+    return LBM_OK;
+}
+
+int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opts *opts,
+               void *dev_buf, size_t buf_bytes, lbm_t **out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_params p;
+    int rc = lbm_derive_params(N, Ra, Pr, cell, storage, opts, &p);
+    if (rc != LBM_OK) return rc;
+    lbm_opts o;
+    lbm_default_opts(&o);
+    if (opts) o = *opts;
+    int block = o.block ? o.block : 256;
+    if (block < 64 || block > 256 || block % 64) return LBM_EINVAL;
+    if (dev_buf && (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return LBM_EINVAL;
+    lbmk::Layout L = lbmk::make_layout(N, storage);
+    if (dev_buf && buf_bytes < L.total) return LBM_ENOMEM;
+
+    lbm_t *h = new (std::nothrow) lbm;
+    if (!h) return LBM_ENOMEM;
+    h->p = p;
+    h->o = o;
+    h->L = L;
+    h->storage = storage;
+    h->block = block;
+    h->geo.N = N;
+    h->geo.N2 = static_cast<uint32_t>(N) * static_cast<uint32_t>(N);
+    h->geo.magic = static_cast<uint32_t>((0x100000000ull + N - 1) / N);
+    h->geo.stride = L.stride;
+    if (dev_buf) {
+        h->buf = dev_buf;
+    } else {
+        hipError_t e = hipMalloc(&h->buf, L.total);
+        if (e != hipSuccess) {
+            delete h;
+            return LBM_ENOMEM;
+        }
+        h->own_buf = true;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_t *h) {
+    if (!h) return LBM_EINVAL;
+    for (hipEvent_t ev : h->events) hipEventDestroy(ev);
+    if (h->own_buf) hipFree(h->buf);
+    delete h;
+    return LBM_OK;
+}
+
+int lbm_get_params(const lbm_t *h, lbm_params *out) {
+    if (!h || !out) return LBM_EINVAL;
+    *out = h->p;
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_t *h, const double *uvwT, void *stream) {
+    if (!h) return LBM_EINVAL;
+    if (!uvwT) return fail(h, LBM_EINVAL, "uvwT is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = lbmk::launch_init(h, uvwT, s);
+    if (e != hipSuccess) return hip_fail(h, e, "init kernel");
+    h->parity = 0;
+    h->t = 0;
+    h->has_flux = false;
+    h->initialised = true;
+    if ((e = lbmk::launch_reset_acc(h, s)) != hipSuccess) return hip_fail(h, e, "reset averages");
+    h->samples = 0;
+    if ((e = lbmk::launch_snapshot(h, s)) != hipSuccess) return hip_fail(h, e, "snapshot");
+    return LBM_OK;
+}
+
+int lbm_get_fields(lbm_t *h, double *out, void *stream) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+    hipError_t e = lbmk::launch_macro(h, out, nullptr, as_stream(stream));
+    return e == hipSuccess ? LBM_OK : hip_fail(h, e, "macro kernel");
+}
+
+int lbm_set_populations(lbm_t *h, const double *in, void *stream) {
+    if (!h) return LBM_EINVAL;
+    if (!in) return fail(h, LBM_EINVAL, "in is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = lbmk::launch_set_pop(h, in, s);
+    if (e != hipSuccess) return hip_fail(h, e, "set populations");
+    h->parity = 0;
+    h->has_flux = false;
+    h->initialised = true;
+    if ((e = lbmk::launch_snapshot(h, s)) != hipSuccess) return hip_fail(h, e, "snapshot");
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_t *h, double *out, void *stream) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+    hipError_t e = lbmk::launch_get_pop(h, out, as_stream(stream));
+    return e == hipSuccess ? LBM_OK : hip_fail(h, e, "get populations");
+}
+
+int lbm_step(lbm_t *h, int64_t n, void *stream) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (n < 0) return fail(h, LBM_EINVAL, "negative step count");
+    hipStream_t s = as_stream(stream);
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e;
+        if (h->profiling) {
+            if (h->events_used + 2 > h->events.size()) {
+                for (int m = 0; m < 2; ++m) {
+                    hipEvent_t ev;
+                    if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(h, e, "event create");
+                    h->events.push_back(ev);
+                }
+            }
+            if ((e = hipEventRecord(h->events[h->events_used], s)) != hipSuccess)
+                return hip_fail(h, e, "event record");
+        }
+        if ((e = lbmk::launch_step(h, h->parity, s)) != hipSuccess) return hip_fail(h, e, "step kernel");
+        if (h->profiling) {
+            if ((e = hipEventRecord(h->events[h->events_used + 1], s)) != hipSuccess)
+                return hip_fail(h, e, "event record");
+            h->events_used += 2;
+        }
+        h->parity ^= 1;
+        h->t += 1;
+        h->has_flux = true;
+        if (h->o.sample_every > 0 && h->t % h->o.sample_every == 0) {
+            if ((e = lbmk::launch_observe(h, true, s)) != hipSuccess) return hip_fail(h, e, "observables");
+            h->samples += 1;
+        }
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_t *h) { return h ? h->t : -1; }
+
+int lbm_observables_raw(lbm_t *h, void *stream, double raw[LBM_NRAW]) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!raw) return fail(h, LBM_EINVAL, "raw is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = lbmk::launch_observe(h, false, s);
+    if (e != hipSuccess) return hip_fail(h, e, "observables");
+    if ((rc = read_res(h, s, lbmk::kResCur, LBM_NRAW, raw)) != LBM_OK) return rc;
+    for (int k = 0; k < LBM_NRAW; ++k)
+        if (!std::isfinite(raw[k])) return fail(h, LBM_EDIVERGED, "non-finite observable");
+    return LBM_OK;
+}
+
+int lbm_nondimensional(const lbm_params *p, const double raw[LBM_NRAW], double out[LBM_NOBS]) {
+    if (!p || !raw || !out) return LBM_EINVAL;
+    const double H = p->H, U = p->U, dT = p->dT, s = std::sqrt(p->Ra * p->Pr);
+    const double nf = H / (p->kappa * dT), ng = H / dT;
+    out[LBM_NU_HOT] = raw[LBM_RAW_FLUX_HOT] * nf;
+    out[LBM_NU_COLD] = -raw[LBM_RAW_FLUX_COLD] * nf;
+    out[LBM_NU_HOT_MID] = raw[LBM_RAW_FLUX_HOT_MID] * nf;
+    out[LBM_NU_COLD_MID] = -raw[LBM_RAW_FLUX_COLD_MID] * nf;
+    out[LBM_NU_HOT_FD] = raw[LBM_RAW_GRAD_HOT] * ng;
+    out[LBM_NU_COLD_FD] = -raw[LBM_RAW_GRAD_COLD] * ng;
+    out[LBM_NU_HOT_MID_FD] = raw[LBM_RAW_GRAD_HOT_MID] * ng;
+    out[LBM_NU_COLD_MID_FD] = -raw[LBM_RAW_GRAD_COLD_MID] * ng;
+    out[LBM_RE_RMS] = std::sqrt(raw[LBM_RAW_U2]) * H / p->nu;
+    out[LBM_RE_W] = std::sqrt(raw[LBM_RAW_W2]) * H / p->nu;
+    const double vt = p->cell == LBM_RAYLEIGH_BENARD ? raw[LBM_RAW_WT] : raw[LBM_RAW_UT];
+    out[LBM_NU_VOL] = 1.0 + s * vt / (U * dT);
+    out[LBM_EPS_U] = raw[LBM_RAW_EPS_U] * H / (U * U * U);
+    out[LBM_EPS_T] = raw[LBM_RAW_EPS_T] * H / (U * dT * dT);
+    out[LBM_NU_KIN] = 1.0 + s * out[LBM_EPS_U];
+    out[LBM_NU_TH] = s * out[LBM_EPS_T];
+    out[LBM_E_KIN] = 0.5 * raw[LBM_RAW_U2] / (U * U);
+    out[LBM_RMS_DRHO] = std::sqrt(raw[LBM_RAW_DRHO2]);
+    out[LBM_MEAN_T] = raw[LBM_RAW_T];
+    out[LBM_RMS_DIV] = std::sqrt(raw[LBM_RAW_DIV2]) * H / U;
+    return LBM_OK;
+}
+
+int lbm_observables(lbm_t *h, void *stream, double *Nu, double *Re, double *eps_u, double *eps_T) {
+    double raw[LBM_NRAW], nd[LBM_NOBS];
+    int rc = lbm_observables_raw(h, stream, raw);
+    if (rc != LBM_OK) return rc;
+    lbm_nondimensional(&h->p, raw, nd);
+    if (Nu) *Nu = 0.5 * (nd[LBM_NU_HOT] + nd[LBM_NU_COLD]);
+    if (Re) *Re = nd[LBM_RE_RMS];
+    if (eps_u) *eps_u = nd[LBM_EPS_U];
+    if (eps_T) *eps_T = nd[LBM_EPS_T];
+    return LBM_OK;
+}
+
+int lbm_averages(lbm_t *h, void *stream, double raw_mean[LBM_NRAW], int64_t *count) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!raw_mean) return fail(h, LBM_EINVAL, "raw_mean is NULL");
+    double acc[LBM_NRAW + 1];
+    if ((rc = read_res(h, as_stream(stream), lbmk::kResAcc, LBM_NRAW + 1, acc)) != LBM_OK) return rc;
+    const double n = acc[LBM_NRAW];
+    if (count) *count = static_cast<int64_t>(n);
+    if (n <= 0) return fail(h, LBM_ESTATE, "no samples since the last reset");
+    for (int k = 0; k < LBM_NRAW; ++k) {
+        raw_mean[k] = acc[k] / n;
+        if (!std::isfinite(raw_mean[k])) return fail(h, LBM_EDIVERGED, "non-finite average");
+    }
+    return LBM_OK;
+}
+
+int lbm_reset_averages(lbm_t *h, void *stream) {
+    if (!h) return LBM_EINVAL;
+    hipError_t e = lbmk::launch_reset_acc(h, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(h, e, "reset averages");
+    h->samples = 0;
+    return LBM_OK;
+}
+
+int lbm_residual(lbm_t *h, void *stream, double *max_dT, double *rel_L1_T, double *rel_L2_u) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = lbmk::launch_residual(h, s);
+    if (e != hipSuccess) return hip_fail(h, e, "residual");
+    double t[5];
+    if ((rc = read_res(h, s, lbmk::kResResid, 5, t)) != LBM_OK) return rc;
+    for (double v : t)
+        if (!std::isfinite(v)) return fail(h, LBM_EDIVERGED, "non-finite residual");
+    auto ratio = [](double a, double b) { return a == 0.0 ? 0.0 : (b == 0.0 ? INFINITY : a / b); };
+    if (max_dT) *max_dT = t[0];
+    if (rel_L1_T) *rel_L1_T = ratio(t[1], t[2]);
+    if (rel_L2_u) *rel_L2_u = ratio(t[3], t[4]);
+    return LBM_OK;
+}
+
+int lbm_profile(lbm_t *h, int enable) {
+    if (!h) return LBM_EINVAL;
+    h->profiling = enable != 0;
+    return LBM_OK;
+}
+
+int lbm_profile_read(lbm_t *h, double *kernel_ms, int64_t *kernels) {
+    if (!h || !kernel_ms || !kernels) return LBM_EINVAL;
+    double total = 0.0;
+    for (size_t k = 0; k + 1 < h->events_used; k += 2) {
+        hipError_t e = hipEventSynchronize(h->events[k + 1]);
+        if (e != hipSuccess) return hip_fail(h, e, "event synchronize");
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, h->events[k], h->events[k + 1])) != hipSuccess)
+            return hip_fail(h, e, "event elapsed");
+        total += ms;
+    }
+    *kernel_ms = total;
+    *kernels = static_cast<int64_t>(h->events_used / 2);
+    h->events_used = 0;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_t *h) { return h ? h->err.c_str() : "NULL handle"; }
+
+const char *lbm_strerror(int status) {
+    switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ERANGE: return "parameters outside the valid range of the scheme";
+    case LBM_ENOMEM: return "buffer too small or allocation failed";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_EDIVERGED: return "non-finite result (diverged)";
+    case LBM_ESTATE: return "call not valid in the current state";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,847 @@
+// kernels.hip -- gfx950 kernels of the coupled D3Q19-MRT / D3Q7-MRT thermal
+// lattice Boltzmann step (Xu, Shi & Xi 2019, arXiv:1903.08882).
+//
+// Storage.  26 population planes (f_0..f_18, g_0..g_6), x fastest, one plane
+// every `stride` elements.  f is stored as the deviation f_i - w_i from the
+// rest equilibrium (rho = 1, u = 0), g as is (its rest equilibrium at the mean
+// wall temperature 0 is zero); FP16 storage scales both by a power of two.
+//
+// Streaming uses the in-place AA pattern, so each step reads and writes the
+// same 26 slots per node and the state needs one copy:
+//   parity 0 (canonical): slot i of node x holds f_i(x, t).
+//     The step collides and writes f_i+(x) into slot opp(i) of the same node.
+//   parity 1 (swapped): slot opp(i) of node x holds f_i+(x, t-1).
+//     The step gathers f_i(x, t) = f_i+(x - e_i, t-1) from slot opp(i) of the
+//     upstream node, collides, and writes f_i+(x) into slot i of x + e_i.
+// A link that crosses a wall never leaves its node: in parity 1 the value
+// coming back from the wall sits in slot i of x itself, and the outgoing value
+// goes to slot opp(i) of x.  The wall rules of Sec. 2.2 / 2.3 are applied on
+// exactly those accesses:
+//   f:             f_opp(x, t+1) =  f_i+(x, t)                  (no slip)
+//   g, fixed T:    g_opp(x, t+1) = -g_i+(x, t) + (6 + a_T)/21 T_w
+//   g, adiabatic:  g_opp(x, t+1) =  g_i+(x, t)
+// Every wall sits half a link from the nodes next to it; D3Q19 diagonal links
+// that cross two walls bounce back the same way, and D3Q7 links cross one.
+#include <type_traits>
+
+#include "lbm_internal.h"
+
+namespace lbmk {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Lattice constants: velocity order of the paper's printed arrays.
+// ---------------------------------------------------------------------------
+constexpr int EX[kQF] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EY[kQF] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int EZ[kQF] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int OPP[kQF] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+constexpr int GX[kQG] = {0, 1, -1, 0, 0, 0, 0};
+constexpr int GY[kQG] = {0, 0, 0, 1, -1, 0, 0};
+constexpr int GZ[kQG] = {0, 0, 0, 0, 0, 1, -1};
+constexpr int GOPP[kQG] = {0, 2, 1, 4, 3, 6, 5};
+
+// Rest weights of f^eq (Sec. 2.2).
+__host__ __device__ constexpr double wrest(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs
+// ---------------------------------------------------------------------------
+struct CF64 { using S = double; using R = double; };
+struct CF32 { using S = float; using R = float; };
+struct CF16 { using S = _Float16; using R = float; };
+
+template <class C>
+__device__ __forceinline__ typename C::R dec(typename C::S v, typename C::R inv_scale) {
+    if constexpr (std::is_same<C, CF16>::value)
+        return static_cast<float>(v) * inv_scale;
+    else
+        return v;
+}
+template <class C>
+__device__ __forceinline__ typename C::S enc(typename C::R v, typename C::R scale) {
+    if constexpr (std::is_same<C, CF16>::value)
+        return static_cast<_Float16>(v * scale);
+    else
+        return v;
+}
+
+// ---------------------------------------------------------------------------
+// Node of a (ceil(N^2 / blockDim), N) launch
+// ---------------------------------------------------------------------------
+struct Node {
+    int x, y, z;
+    uint64_t n;
+};
+
+__device__ __forceinline__ bool node_of(const Geo &g, Node &d) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    d.z = blockIdx.y;
+    d.y = __umulhi(r, g.magic);
+    d.x = static_cast<int>(r) - d.y * g.N;
+    d.n = static_cast<uint64_t>(d.z) * g.N2 + r;
+    return r < g.N2;
+}
+
+// x - e outside the box?  (the upstream node of link e)
+__device__ __forceinline__ bool up_out(int ex, int ey, int ez, const Node &d, int N) {
+    return (ex > 0 && d.x == 0) || (ex < 0 && d.x == N - 1) || (ey > 0 && d.y == 0) ||
+           (ey < 0 && d.y == N - 1) || (ez > 0 && d.z == 0) || (ez < 0 && d.z == N - 1);
+}
+// x + e outside the box?  (the downstream node of link e)
+__device__ __forceinline__ bool down_out(int ex, int ey, int ez, const Node &d, int N) {
+    return (ex > 0 && d.x == N - 1) || (ex < 0 && d.x == 0) || (ey > 0 && d.y == N - 1) ||
+           (ey < 0 && d.y == 0) || (ez > 0 && d.z == N - 1) || (ez < 0 && d.z == 0);
+}
+__device__ __forceinline__ int64_t link_offset(int ex, int ey, int ez, const Geo &g) {
+    return static_cast<int64_t>(ex) + static_cast<int64_t>(ey) * g.N +
+           static_cast<int64_t>(ez) * static_cast<int64_t>(g.N2);
+}
+
+// Component of D3Q7 link j along the isothermal axis (x side-heated, z RB).
+template <int CELL>
+__device__ __forceinline__ constexpr int iso_comp(int j) {
+    return CELL == LBM_SIDE_HEATED ? GX[j] : GZ[j];
+}
+
+// ---------------------------------------------------------------------------
+// Gather the pre-collision populations f_i(x, t), g_i(x, t) of a node.
+// SW = false: canonical storage; SW = true: swapped storage (see top).
+// f is returned as deviations f_i - w_i.
+// ---------------------------------------------------------------------------
+template <class C, int CELL, bool SW>
+__device__ __forceinline__ void gather(const typename C::S *__restrict__ pop, const Geo &g,
+                                       const Node &d, const Coef<typename C::R> &c,
+                                       typename C::R f[kQF], typename C::R h[kQG]) {
+    using R = typename C::R;
+#pragma unroll
+    for (int i = 0; i < kQF; ++i) {
+        if constexpr (!SW) {
+            f[i] = dec<C>(pop[static_cast<uint64_t>(i) * g.stride + d.n], c.isf);
+        } else {
+            const bool out = up_out(EX[i], EY[i], EZ[i], d, g.N);
+            const uint64_t idx = out ? d.n : d.n - link_offset(EX[i], EY[i], EZ[i], g);
+            const uint64_t q = out ? i : OPP[i];
+            f[i] = dec<C>(pop[q * g.stride + idx], c.isf);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kQG; ++j) {
+        if constexpr (!SW) {
+            h[j] = dec<C>(pop[static_cast<uint64_t>(kQF + j) * g.stride + d.n], c.isg);
+        } else {
+            const bool out = up_out(GX[j], GY[j], GZ[j], d, g.N);
+            const uint64_t idx = out ? d.n : d.n - link_offset(GX[j], GY[j], GZ[j], g);
+            const uint64_t q = kQF + (out ? j : GOPP[j]);
+            R v = dec<C>(pop[q * g.stride + idx], c.isg);
+            const int comp = iso_comp<CELL>(j);
+            // arrived through the wall at the upstream side: anti-bounce-back
+            if (comp != 0 && out) v = (comp > 0 ? c.abb_hot : c.abb_cold) - v;
+            h[j] = v;
+        }
+    }
+}
+
+// Scatter the post-collision populations (see top for the two storage states).
+template <class C, int CELL, bool SW>
+__device__ __forceinline__ void scatter(typename C::S *__restrict__ pop, const Geo &g,
+                                        const Node &d, const Coef<typename C::R> &c,
+                                        const typename C::R f[kQF], const typename C::R h[kQG]) {
+    using R = typename C::R;
+#pragma unroll
+    for (int i = 0; i < kQF; ++i) {
+        if constexpr (!SW) {
+            pop[static_cast<uint64_t>(OPP[i]) * g.stride + d.n] = enc<C>(f[i], c.sf);
+        } else {
+            const bool out = down_out(EX[i], EY[i], EZ[i], d, g.N);
+            const uint64_t idx = out ? d.n : d.n + link_offset(EX[i], EY[i], EZ[i], g);
+            const uint64_t q = out ? OPP[i] : i;
+            pop[q * g.stride + idx] = enc<C>(f[i], c.sf);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kQG; ++j) {
+        if constexpr (!SW) {
+            pop[static_cast<uint64_t>(kQF + GOPP[j]) * g.stride + d.n] = enc<C>(h[j], c.sg);
+        } else {
+            const bool out = down_out(GX[j], GY[j], GZ[j], d, g.N);
+            const uint64_t idx = out ? d.n : d.n + link_offset(GX[j], GY[j], GZ[j], g);
+            const uint64_t q = kQF + (out ? GOPP[j] : j);
+            R v = h[j];
+            const int comp = iso_comp<CELL>(j);
+            // leaves through the wall at the downstream side: anti-bounce-back
+            if (comp != 0 && out) v = (comp > 0 ? c.abb_cold : c.abb_hot) - v;
+            pop[q * g.stride + idx] = enc<C>(v, c.sg);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic variables (Sec. 2.2, 2.3) from the deviations:
+//   rho = 1 + sum f', T = sum g, F_z = rho g beta (T - T0),
+//   rho u = sum e f' + F/2 (the rest weights carry no momentum).
+// ---------------------------------------------------------------------------
+template <class R>
+struct Macro {
+    R drho, jx, jy, jz, T, Fz, rho, ux, uy, uz;
+};
+
+template <class R>
+__device__ __forceinline__ Macro<R> macros(const R f[kQF], const R h[kQG], const Coef<R> &c) {
+    Macro<R> m;
+    const R sax = (f[1] + f[2]) + (f[3] + f[4]) + (f[5] + f[6]);
+    const R sdg = ((f[7] + f[10]) + (f[8] + f[9])) + ((f[11] + f[14]) + (f[12] + f[13])) +
+                  ((f[15] + f[18]) + (f[16] + f[17]));
+    m.drho = f[0] + sax + sdg;
+    m.jx = (f[1] - f[2]) + (f[7] - f[10]) - (f[8] - f[9]) + (f[11] - f[14]) - (f[12] - f[13]);
+    m.jy = (f[3] - f[4]) + (f[7] - f[10]) + (f[8] - f[9]) + (f[15] - f[18]) - (f[16] - f[17]);
+    m.jz = (f[5] - f[6]) + (f[11] - f[14]) + (f[12] - f[13]) + (f[15] - f[18]) + (f[16] - f[17]);
+    m.T = h[0] + (h[1] + h[2]) + (h[3] + h[4]) + (h[5] + h[6]);
+    m.rho = R(1) + m.drho;
+    m.Fz = m.rho * c.gbeta * (m.T - c.T0);
+    m.jz += R(0.5) * m.Fz;
+    const R ir = R(1) / m.rho;
+    m.ux = m.jx * ir;
+    m.uy = m.jy * ir;
+    m.uz = m.jz * ir;
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one node, in place (Eq. MRT with F' = M^-1 (I - S/2) M F~ and
+// Eq. MRT_T).  M and N have integer, mutually orthogonal rows, so
+// m = M f' is taken through the opposite-pair sums s and differences d, and
+// f+ = f + M^T diag(1/|M_k|^2) dm is expanded back the same way.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ Macro<R> collide(R f[kQF], R h[kQG], const Coef<R> &c) {
+    const Macro<R> mc = macros(f, h, c);
+    const R s1 = f[1] + f[2], d1 = f[1] - f[2];
+    const R s3 = f[3] + f[4], d3 = f[3] - f[4];
+    const R s5 = f[5] + f[6], d5 = f[5] - f[6];
+    const R s7 = f[7] + f[10], d7 = f[7] - f[10];
+    const R s8 = f[8] + f[9], d8 = f[8] - f[9];
+    const R s11 = f[11] + f[14], d11 = f[11] - f[14];
+    const R s12 = f[12] + f[13], d12 = f[12] - f[13];
+    const R s15 = f[15] + f[18], d15 = f[15] - f[18];
+    const R s16 = f[16] + f[17], d16 = f[16] - f[17];
+    const R sax = s1 + s3 + s5;
+    const R pxy = s7 + s8, pxz = s11 + s12, pyz = s15 + s16;
+    const R sdg = pxy + pxz + pyz;
+
+    const R jx = mc.jx, jy = mc.jy, jz = mc.jz;   // rho u (force corrected)
+    const R ux = mc.ux, uy = mc.uy, uz = mc.uz;
+    const R rxx = jx * ux, ryy = jy * uy, rzz = jz * uz;
+    const R ruu = rxx + ryy + rzz;
+    const R txx = R(2) * rxx - ryy - rzz;
+    const R tww = ryy - rzz;
+
+    // m - m^eq; the rest weights contribute -11 to e and 3 to eps (m^eq at
+    // rho = 1, u = 0), hence the drho terms.
+    const R ne_e = (R(-30) * f[0] - R(11) * sax + R(8) * sdg) + R(11) * mc.drho - R(19) * ruu;
+    const R ne_eps = (R(12) * f[0] - R(4) * sax + sdg) - R(3) * mc.drho + R(5.5) * ruu;
+    const R ne_pxx = (R(2) * s1 - s3 - s5 + pxy + pxz - R(2) * pyz) - txx;
+    const R ne_qxx = (R(-4) * s1 + R(2) * (s3 + s5) + pxy + pxz - R(2) * pyz) + R(0.5) * txx;
+    const R ne_pww = (s3 - s5 + pxy - pxz) - tww;
+    const R ne_qww = (R(-2) * s3 + R(2) * s5 + pxy - pxz) + R(0.5) * tww;
+    const R ne_xy = (s7 - s8) - jx * uy;
+    const R ne_yz = (s15 - s16) - jy * uz;
+    const R ne_xz = (s11 - s12) - jx * uz;
+    const R ne_qx = (R(-4) * d1 + d7 - d8 + d11 - d12) + R(2.0 / 3.0) * jx;
+    const R ne_qy = (R(-4) * d3 + d7 + d8 + d15 - d16) + R(2.0 / 3.0) * jy;
+    const R ne_qz = (R(-4) * d5 + d11 + d12 + d15 + d16) + R(2.0 / 3.0) * jz;
+    const R ne_mx = d7 - d8 - d11 + d12;
+    const R ne_my = -d7 - d8 + d15 - d16;
+    const R ne_mz = d11 + d12 - d15 - d16;
+
+    // dm_k = -s_k (m_k - m^eq_k) + (1 - s_k/2) (M F~)_k with F = (0, 0, F_z);
+    // the conserved rows give dm = 0 (rho) and F (momentum).  Divided by |M_k|^2.
+    const R sa = c.s_a, sb = c.s_b;
+    const R ha = R(1) - R(0.5) * sa, hb = R(1) - R(0.5) * sb;
+    const R Fz = mc.Fz, uF = uz * Fz;
+    const R a_e = (ha * R(38) * uF - sa * ne_e) * R(1.0 / 2394.0);
+    const R a_eps = (-ha * R(11) * uF - sa * ne_eps) * R(1.0 / 252.0);
+    const R a_pxx = (-ha * R(2) * uF - sa * ne_pxx) * R(1.0 / 36.0);
+    const R a_qxx = (ha * uF - sa * ne_qxx) * R(1.0 / 72.0);
+    const R a_pww = (-ha * R(2) * uF - sa * ne_pww) * R(1.0 / 12.0);
+    const R a_qww = (ha * uF - sa * ne_qww) * R(1.0 / 24.0);
+    const R a_xy = -sa * ne_xy * R(0.25);
+    const R a_yz = (ha * uy * Fz - sa * ne_yz) * R(0.25);
+    const R a_xz = (ha * ux * Fz - sa * ne_xz) * R(0.25);
+    const R a_jz = Fz * R(0.1);
+    const R a_qx = -sb * ne_qx * R(1.0 / 40.0);
+    const R a_qy = -sb * ne_qy * R(1.0 / 40.0);
+    const R a_qz = (-hb * R(2.0 / 3.0) * Fz - sb * ne_qz) * R(1.0 / 40.0);
+    const R a_mx = -sb * ne_mx * R(0.125);
+    const R a_my = -sb * ne_my * R(0.125);
+    const R a_mz = -sb * ne_mz * R(0.125);
+
+    // even part (same for i and opp(i)) ...
+    const R Eax = R(-11) * a_e - R(4) * a_eps;
+    const R Ex = Eax + R(2) * a_pxx - R(4) * a_qxx;
+    const R Eyz = Eax - a_pxx + R(2) * a_qxx;
+    const R Ey = Eyz + a_pww - R(2) * a_qww;
+    const R Ez = Eyz - a_pww + R(2) * a_qww;
+    const R Dc = R(8) * a_e + a_eps;
+    const R Pxy = Dc + a_pxx + a_qxx + a_pww + a_qww;
+    const R Pxz = Dc + a_pxx + a_qxx - a_pww - a_qww;
+    const R Pyz = Dc - R(2) * (a_pxx + a_qxx);
+    // ... and odd part (sign flips for opp(i))
+    const R Ox = R(-4) * a_qx;
+    const R Oy = R(-4) * a_qy;
+    const R Oz = a_jz - R(4) * a_qz;
+    const R cx = a_qx, cy = a_qy, cz = a_jz + a_qz;
+    const R O7 = cx + cy + a_mx - a_my;
+    const R O8 = -cx + cy - a_mx - a_my;
+    const R O11 = cx + cz - a_mx + a_mz;
+    const R O12 = -cx + cz + a_mx + a_mz;
+    const R O15 = cy + cz + a_my - a_mz;
+    const R O16 = -cy + cz - a_my - a_mz;
+
+    f[0] += R(-30) * a_e + R(12) * a_eps;
+    f[1] += Ex + Ox;
+    f[2] += Ex - Ox;
+    f[3] += Ey + Oy;
+    f[4] += Ey - Oy;
+    f[5] += Ez + Oz;
+    f[6] += Ez - Oz;
+    f[7] += Pxy + a_xy + O7;
+    f[10] += Pxy + a_xy - O7;
+    f[8] += Pxy - a_xy + O8;
+    f[9] += Pxy - a_xy - O8;
+    f[11] += Pxz + a_xz + O11;
+    f[14] += Pxz + a_xz - O11;
+    f[12] += Pxz - a_xz + O12;
+    f[13] += Pxz - a_xz - O12;
+    f[15] += Pyz + a_yz + O15;
+    f[18] += Pyz + a_yz - O15;
+    f[16] += Pyz - a_yz + O16;
+    f[17] += Pyz - a_yz - O16;
+
+    // D3Q7: n = N g, n^eq = (T, uT, vT, wT, a_T T, 0, 0), Q = diag(0, q_k x3, q_e, q_nu x2)
+    const R T = mc.T;
+    const R n1 = h[1] - h[2], n2 = h[3] - h[4], n3 = h[5] - h[6];
+    const R p1 = h[1] + h[2], p2 = h[3] + h[4], p3 = h[5] + h[6];
+    const R n4 = T - R(7) * h[0];
+    const R n5 = R(2) * p1 - p2 - p3;
+    const R n6 = p2 - p3;
+    const R b1 = -c.q_k * (n1 - ux * T) * R(0.5);
+    const R b2 = -c.q_k * (n2 - uy * T) * R(0.5);
+    const R b3 = -c.q_k * (n3 - uz * T) * R(0.5);
+    const R b4 = -c.q_e * (n4 - c.a_T * T) * R(1.0 / 42.0);
+    const R b5 = -c.q_nu * n5 * R(1.0 / 12.0);
+    const R b6 = -c.q_nu * n6 * R(0.25);
+    const R c1 = b4 + R(2) * b5, c2 = b4 - b5 + b6, c3 = b4 - b5 - b6;
+    h[0] += R(-6) * b4;
+    h[1] += c1 + b1;
+    h[2] += c1 - b1;
+    h[3] += c2 + b2;
+    h[4] += c2 - b2;
+    h[5] += c3 + b3;
+    h[6] += c3 - b3;
+    return mc;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <class C, int CELL, bool SW>
+__global__ __launch_bounds__(256) void k_step(typename C::S *__restrict__ pop, Geo g,
+                                              Coef<typename C::R> c) {
+    using R = typename C::R;
+    Node d;
+    if (!node_of(g, d)) return;
+    R f[kQF], h[kQG];
+    gather<C, CELL, SW>(pop, g, d, c, f, h);
+    collide(f, h, c);
+    scatter<C, CELL, SW>(pop, g, d, c, f, h);
+}
+
+// f = f^eq(1, u) (Sec. 2.2), g = g^eq(T, u) (Sec. 2.3), canonical slots.
+template <class C>
+__global__ __launch_bounds__(256) void k_init(typename C::S *__restrict__ pop, Geo g,
+                                              Coef<typename C::R> c, const double *__restrict__ uvwT,
+                                              double wT0, double wT1, double aT) {
+    Node d;
+    if (!node_of(g, d)) return;
+    const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+    const double u = uvwT[d.n], v = uvwT[V + d.n], w = uvwT[2 * V + d.n], T = uvwT[3 * V + d.n];
+    const double uu = u * u + v * v + w * w;
+#pragma unroll
+    for (int i = 0; i < kQF; ++i) {
+        const double eu = EX[i] * u + EY[i] * v + EZ[i] * w;
+        const double fdev = wrest(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        pop[static_cast<uint64_t>(i) * g.stride + d.n] =
+            enc<C>(static_cast<typename C::R>(fdev), c.sf);
+    }
+    const double k = 21.0 / (6.0 + aT);
+#pragma unroll
+    for (int j = 0; j < kQG; ++j) {
+        const double eu = GX[j] * u + GY[j] * v + GZ[j] * w;
+        const double gv = (j == 0 ? wT0 : wT1) * T * (1.0 + k * eu);
+        pop[static_cast<uint64_t>(kQF + j) * g.stride + d.n] =
+            enc<C>(static_cast<typename C::R>(gv), c.sg);
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_set_pop(typename C::S *__restrict__ pop, Geo g,
+                                                 Coef<typename C::R> c,
+                                                 const double *__restrict__ in) {
+    Node d;
+    if (!node_of(g, d)) return;
+    const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+#pragma unroll
+    for (int i = 0; i < kQF; ++i)
+        pop[static_cast<uint64_t>(i) * g.stride + d.n] =
+            enc<C>(static_cast<typename C::R>(in[i * V + d.n] - wrest(i)), c.sf);
+#pragma unroll
+    for (int j = 0; j < kQG; ++j)
+        pop[static_cast<uint64_t>(kQF + j) * g.stride + d.n] =
+            enc<C>(static_cast<typename C::R>(in[(kQF + j) * V + d.n]), c.sg);
+}
+
+template <class C, int CELL, bool SW>
+__global__ __launch_bounds__(256) void k_get_pop(const typename C::S *__restrict__ pop, Geo g,
+                                                 Coef<typename C::R> c, double *__restrict__ out) {
+    using R = typename C::R;
+    Node d;
+    if (!node_of(g, d)) return;
+    const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+    R f[kQF], h[kQG];
+    gather<C, CELL, SW>(pop, g, d, c, f, h);
+#pragma unroll
+    for (int i = 0; i < kQF; ++i) out[i * V + d.n] = static_cast<double>(f[i]) + wrest(i);
+#pragma unroll
+    for (int j = 0; j < kQG; ++j) out[(kQF + j) * V + d.n] = static_cast<double>(h[j]);
+}
+
+// Macro planes [rho, u, v, w, T] and, at the isothermal walls, the heat that
+// entered through each wall link during the last step: the population that
+// came back from the wall is g_in = -g_out+ + abb, so abb - 2 g_out+ equals
+// 2 g_in - abb (Sec. 2.3 anti-bounce-back).
+template <class C, int CELL, bool SW>
+__global__ __launch_bounds__(256) void k_macro(const typename C::S *__restrict__ pop, Geo g,
+                                               Coef<typename C::R> c, double *__restrict__ macro,
+                                               double *__restrict__ wall, double abb_hot,
+                                               double abb_cold) {
+    using R = typename C::R;
+    Node d;
+    if (!node_of(g, d)) return;
+    const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+    R f[kQF], h[kQG];
+    gather<C, CELL, SW>(pop, g, d, c, f, h);
+    const Macro<R> m = macros(f, h, c);
+    macro[d.n] = 1.0 + static_cast<double>(m.drho);
+    macro[V + d.n] = m.ux;
+    macro[2 * V + d.n] = m.uy;
+    macro[3 * V + d.n] = m.uz;
+    macro[4 * V + d.n] = m.T;
+    if (wall == nullptr) return;
+    if constexpr (CELL == LBM_SIDE_HEATED) {
+        const uint64_t w2 = d.y + static_cast<uint64_t>(g.N) * d.z;
+        if (d.x == 0) wall[w2] = 2.0 * static_cast<double>(h[1]) - abb_hot;
+        if (d.x == g.N - 1) wall[g.N2 + w2] = 2.0 * static_cast<double>(h[2]) - abb_cold;
+    } else {
+        const uint64_t w2 = d.x + static_cast<uint64_t>(g.N) * d.y;
+        if (d.z == 0) wall[w2] = 2.0 * static_cast<double>(h[5]) - abb_hot;
+        if (d.z == g.N - 1) wall[g.N2 + w2] = 2.0 * static_cast<double>(h[6]) - abb_cold;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (FP64, fixed order: deterministic)
+// ---------------------------------------------------------------------------
+template <int K, bool MAX0>
+__device__ __forceinline__ void block_reduce_to(double (&v)[K], double *__restrict__ out) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double t = __shfl_down(v[k], o, 64);
+            v[k] = (MAX0 && k == 0) ? fmax(v[k], t) : v[k] + t;
+        }
+    __shared__ double sm[kRedBlock / 64][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sm[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        double s = sm[0][k];
+        for (int w = 1; w < kRedBlock / 64; ++w) s = (MAX0 && k == 0) ? fmax(s, sm[w][k]) : s + sm[w][k];
+        out[k] = s;
+    }
+}
+
+// One-sided / central derivative of a plane along one axis (stride s between
+// neighbours, k the node's index on that axis).  See the header of lbm.h.
+__device__ __forceinline__ double dfd(const double *__restrict__ phi, uint64_t n, int64_t s, int k,
+                                      int N, double w_lo, double w_hi, bool mirror) {
+    if (k > 0 && k < N - 1) return 0.5 * (phi[n + s] - phi[n - s]);
+    if (k == 0) {
+        const double a = phi[n], b = phi[n + s];
+        return mirror ? 0.5 * (b - a) : (-4.0 / 3.0) * w_lo + a + b * (1.0 / 3.0);
+    }
+    const double a = phi[n], b = phi[n - s];
+    return mirror ? 0.5 * (a - b) : (4.0 / 3.0) * w_hi - a - b * (1.0 / 3.0);
+}
+
+struct ObsArgs {
+    double nu, kappa, T_hot, T_cold;
+};
+
+template <int CELL>
+__global__ __launch_bounds__(kRedBlock) void k_observe(Geo g, ObsArgs a,
+                                                       const double *__restrict__ macro,
+                                                       const double *__restrict__ wall,
+                                                       double *__restrict__ part) {
+    Node d;
+    const bool live = node_of(g, d);
+    double v[LBM_NRAW];
+#pragma unroll
+    for (int k = 0; k < LBM_NRAW; ++k) v[k] = 0.0;
+    if (live) {
+        const int N = g.N;
+        const uint64_t V = static_cast<uint64_t>(g.N2) * N;
+        const double *rho = macro, *T = macro + 4 * V;
+        const double *U[3] = {macro + V, macro + 2 * V, macro + 3 * V};
+        const uint64_t n = d.n;
+        const int c3[3] = {d.x, d.y, d.z};
+        const int64_t st[3] = {1, N, static_cast<int64_t>(g.N2)};
+        constexpr int iso = CELL == LBM_SIDE_HEATED ? 0 : 2;
+        double du[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) du[i][j] = dfd(U[j], n, st[i], c3[i], N, 0.0, 0.0, false);
+        double dT[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dT[i] = dfd(T, n, st[i], c3[i], N, a.T_hot, a.T_cold, i != iso);
+        double eu = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double sij = du[i][j] + du[j][i];
+                eu += sij * sij;
+            }
+        const double u = U[0][n], vv = U[1][n], w = U[2][n], Tn = T[n], dr = rho[n] - 1.0;
+        const double div = du[0][0] + du[1][1] + du[2][2];
+        v[LBM_RAW_U2] = u * u + vv * vv + w * w;
+        v[LBM_RAW_W2] = w * w;
+        v[LBM_RAW_WT] = w * Tn;
+        v[LBM_RAW_UT] = u * Tn;
+        v[LBM_RAW_EPS_U] = 0.5 * a.nu * eu;
+        v[LBM_RAW_EPS_T] = a.kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
+        v[LBM_RAW_DRHO2] = dr * dr;
+        v[LBM_RAW_T] = Tn;
+        v[LBM_RAW_DRHO] = dr;
+        v[LBM_RAW_DIV2] = div * div;
+        const int k = c3[iso];
+        const int mid_lo = (N - 1) / 2, mid_hi = N / 2;
+        const double wm = (d.y == mid_lo || d.y == mid_hi) ? (mid_lo == mid_hi ? 1.0 : 0.5) : 0.0;
+        const uint64_t w2 = CELL == LBM_SIDE_HEATED ? d.y + static_cast<uint64_t>(N) * d.z
+                                                    : d.x + static_cast<uint64_t>(N) * d.y;
+        if (k == 0) {
+            const double q = wall ? wall[w2] : 0.0;
+            const double gr = -(-8.0 * a.T_hot + 9.0 * Tn - T[n + st[iso]]) * (1.0 / 3.0);
+            v[LBM_RAW_FLUX_HOT] = q;
+            v[LBM_RAW_FLUX_HOT_MID] = wm * q;
+            v[LBM_RAW_GRAD_HOT] = gr;
+            v[LBM_RAW_GRAD_HOT_MID] = wm * gr;
+        }
+        if (k == N - 1) {
+            const double q = wall ? wall[g.N2 + w2] : 0.0;
+            const double gr = (8.0 * a.T_cold - 9.0 * Tn + T[n - st[iso]]) * (1.0 / 3.0);
+            v[LBM_RAW_FLUX_COLD] = q;
+            v[LBM_RAW_FLUX_COLD_MID] = wm * q;
+            v[LBM_RAW_GRAD_COLD] = gr;
+            v[LBM_RAW_GRAD_COLD_MID] = wm * gr;
+        }
+    }
+    const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+    block_reduce_to<LBM_NRAW, false>(v, part + static_cast<uint64_t>(b) * kNPart);
+}
+
+// Sum the block partials in a fixed order and scale to means.
+__global__ __launch_bounds__(kRedBlock) void k_finalize_obs(const double *__restrict__ part,
+                                                            uint32_t nblk, double inv_V,
+                                                            double inv_A, double inv_L,
+                                                            double *__restrict__ res,
+                                                            int accumulate) {
+    double v[LBM_NRAW];
+#pragma unroll
+    for (int k = 0; k < LBM_NRAW; ++k) v[k] = 0.0;
+    for (uint32_t b = threadIdx.x; b < nblk; b += kRedBlock)
+#pragma unroll
+        for (int k = 0; k < LBM_NRAW; ++k) v[k] += part[static_cast<uint64_t>(b) * kNPart + k];
+    __shared__ double tot[LBM_NRAW];
+    block_reduce_to<LBM_NRAW, false>(v, tot);
+    __syncthreads();
+    if (threadIdx.x < LBM_NRAW) {
+        const int k = threadIdx.x;
+        const double s = (k <= LBM_RAW_FLUX_COLD || k == LBM_RAW_GRAD_HOT || k == LBM_RAW_GRAD_COLD)
+                             ? inv_A
+                             : (k < LBM_RAW_U2 ? inv_L : inv_V);
+        const double m = tot[k] * s;
+        res[kResCur + k] = m;
+        if (accumulate) res[kResAcc + k] += m;
+    }
+    if (threadIdx.x == 0 && accumulate) res[kResAcc + LBM_NRAW] += 1.0;
+}
+
+__global__ void k_reset_acc(double *__restrict__ res) {
+    if (threadIdx.x <= LBM_NRAW) res[kResAcc + threadIdx.x] = 0.0;
+}
+
+// Residual partials (max |dT|, sum |dT|, sum |T_old|, sum |du|, sum |u_old|),
+// then the snapshot takes the current state.
+__global__ __launch_bounds__(kRedBlock) void k_residual(Geo g, const double *__restrict__ macro,
+                                                        double *__restrict__ snap,
+                                                        double *__restrict__ part) {
+    Node d;
+    const bool live = node_of(g, d);
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        const uint64_t V = static_cast<uint64_t>(g.N2) * g.N, n = d.n;
+        const double T = macro[4 * V + n], Ts = snap[3 * V + n];
+        double s = 0.0, so = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double u = macro[(1 + a) * V + n], us = snap[a * V + n];
+            s += (u - us) * (u - us);
+            so += us * us;
+            snap[a * V + n] = u;
+        }
+        snap[3 * V + n] = T;
+        v[0] = fabs(T - Ts);
+        v[1] = v[0];
+        v[2] = fabs(Ts);
+        v[3] = sqrt(s);
+        v[4] = sqrt(so);
+    }
+    const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+    block_reduce_to<5, true>(v, part + static_cast<uint64_t>(b) * kNPart);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_finalize_residual(const double *__restrict__ part,
+                                                                 uint32_t nblk,
+                                                                 double *__restrict__ res) {
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < nblk; b += kRedBlock)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const double x = part[static_cast<uint64_t>(b) * kNPart + k];
+            v[k] = k == 0 ? fmax(v[k], x) : v[k] + x;
+        }
+    __shared__ double tot[5];
+    block_reduce_to<5, true>(v, tot);
+    __syncthreads();
+    if (threadIdx.x < 5) res[kResResid + threadIdx.x] = tot[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side helpers
+// ---------------------------------------------------------------------------
+template <class R>
+Coef<R> make_coef(const lbm_t *h) {
+    const lbm_params &p = h->p;
+    Coef<R> c;
+    c.s_a = static_cast<R>(p.s_e);
+    c.s_b = static_cast<R>(p.s_q);
+    c.q_k = static_cast<R>(p.q_k);
+    c.q_e = static_cast<R>(p.q_e);
+    c.q_nu = static_cast<R>(p.q_nu);
+    c.a_T = static_cast<R>(p.a_T);
+    c.gbeta = static_cast<R>(p.gbeta);
+    c.T0 = static_cast<R>(p.T0);
+    c.abb_hot = static_cast<R>((6.0 + p.a_T) / 21.0 * p.T_hot);
+    c.abb_cold = static_cast<R>((6.0 + p.a_T) / 21.0 * p.T_cold);
+    const bool half = h->storage == LBM_FP16S;
+    c.sf = static_cast<R>(half ? 1024.0 : 1.0);
+    c.isf = static_cast<R>(half ? 1.0 / 1024.0 : 1.0);
+    c.sg = static_cast<R>(1.0);
+    c.isg = static_cast<R>(1.0);
+    return c;
+}
+
+dim3 grid_of(const lbm_t *h, int block) {
+    return dim3((h->geo.N2 + block - 1) / block, h->geo.N, 1);
+}
+
+template <class C>
+typename C::S *pop_ptr(const lbm_t *h) {
+    return reinterpret_cast<typename C::S *>(static_cast<char *>(h->buf) + h->L.off_pop);
+}
+double *dptr(const lbm_t *h, size_t off) {
+    return reinterpret_cast<double *>(static_cast<char *>(h->buf) + off);
+}
+
+// Dispatch a functor on the storage codec of the handle.
+template <class F>
+hipError_t with_codec(const lbm_t *h, F &&fn) {
+    switch (h->storage) {
+    case LBM_FP64: return fn(CF64{});
+    case LBM_FP32: return fn(CF32{});
+    default: return fn(CF16{});
+    }
+}
+
+template <class C, int CELL, bool SW>
+void step_one(const lbm_t *h, hipStream_t s) {
+    k_step<C, CELL, SW><<<grid_of(h, h->block), h->block, 0, s>>>(
+        pop_ptr<C>(h), h->geo, make_coef<typename C::R>(h));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_step(const lbm_t *h, int parity, hipStream_t s) {
+    return with_codec(h, [&](auto cd) {
+        using C = decltype(cd);
+        if (h->p.cell == LBM_SIDE_HEATED) {
+            if (parity) step_one<C, LBM_SIDE_HEATED, true>(h, s);
+            else step_one<C, LBM_SIDE_HEATED, false>(h, s);
+        } else {
+            if (parity) step_one<C, LBM_RAYLEIGH_BENARD, true>(h, s);
+            else step_one<C, LBM_RAYLEIGH_BENARD, false>(h, s);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_init(const lbm_t *h, const double *uvwT, hipStream_t s) {
+    return with_codec(h, [&](auto cd) {
+        using C = decltype(cd);
+        k_init<C><<<grid_of(h, 256), 256, 0, s>>>(pop_ptr<C>(h), h->geo,
+                                                 make_coef<typename C::R>(h), uvwT, h->p.wT0,
+                                                 h->p.wT1, h->p.a_T);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_pop(const lbm_t *h, const double *in, hipStream_t s) {
+    return with_codec(h, [&](auto cd) {
+        using C = decltype(cd);
+        k_set_pop<C><<<grid_of(h, 256), 256, 0, s>>>(pop_ptr<C>(h), h->geo,
+                                                    make_coef<typename C::R>(h), in);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_get_pop(const lbm_t *h, double *out, hipStream_t s) {
+    return with_codec(h, [&](auto cd) {
+        using C = decltype(cd);
+        auto c = make_coef<typename C::R>(h);
+        const dim3 gr = grid_of(h, 256);
+        const typename C::S *p = pop_ptr<C>(h);
+        if (h->p.cell == LBM_SIDE_HEATED) {
+            if (h->parity) k_get_pop<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, h->geo, c, out);
+            else k_get_pop<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, h->geo, c, out);
+        } else {
+            if (h->parity) k_get_pop<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, h->geo, c, out);
+            else k_get_pop<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, h->geo, c, out);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_macro(const lbm_t *h, double *macro_out, double *wall_out, hipStream_t s) {
+    const double abb_hot = (6.0 + h->p.a_T) / 21.0 * h->p.T_hot;
+    const double abb_cold = (6.0 + h->p.a_T) / 21.0 * h->p.T_cold;
+    return with_codec(h, [&](auto cd) {
+        using C = decltype(cd);
+        auto c = make_coef<typename C::R>(h);
+        const dim3 gr = grid_of(h, 256);
+        const typename C::S *p = pop_ptr<C>(h);
+        if (h->p.cell == LBM_SIDE_HEATED) {
+            if (h->parity)
+                k_macro<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+            else
+                k_macro<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+        } else {
+            if (h->parity)
+                k_macro<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+            else
+                k_macro<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s) {
+    double *macro = dptr(h, h->L.off_macro);
+    double *wall = h->has_flux ? dptr(h, h->L.off_wall) : nullptr;
+    hipError_t e = launch_macro(h, macro, dptr(h, h->L.off_wall), s);
+    if (e != hipSuccess) return e;
+    ObsArgs a{h->p.nu, h->p.kappa, h->p.T_hot, h->p.T_cold};
+    double *part = dptr(h, h->L.off_part);
+    const dim3 gr = grid_of(h, kRedBlock);
+    if (h->p.cell == LBM_SIDE_HEATED)
+        k_observe<LBM_SIDE_HEATED><<<gr, kRedBlock, 0, s>>>(h->geo, a, macro, wall, part);
+    else
+        k_observe<LBM_RAYLEIGH_BENARD><<<gr, kRedBlock, 0, s>>>(h->geo, a, macro, wall, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const double N = h->geo.N;
+    k_finalize_obs<<<1, kRedBlock, 0, s>>>(part, h->L.nblk_red, 1.0 / (N * N * N), 1.0 / (N * N),
+                                           1.0 / N, dptr(h, h->L.off_res), accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_acc(const lbm_t *h, hipStream_t s) {
+    k_reset_acc<<<1, 64, 0, s>>>(dptr(h, h->L.off_res));
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const lbm_t *h, hipStream_t s) {
+    double *macro = dptr(h, h->L.off_macro);
+    hipError_t e = launch_macro(h, macro, nullptr, s);
+    if (e != hipSuccess) return e;
+    double *part = dptr(h, h->L.off_part);
+    k_residual<<<grid_of(h, kRedBlock), kRedBlock, 0, s>>>(h->geo, macro, dptr(h, h->L.off_snap), part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_finalize_residual<<<1, kRedBlock, 0, s>>>(part, h->L.nblk_red, dptr(h, h->L.off_res));
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const lbm_t *h, hipStream_t s) {
+    double *macro = dptr(h, h->L.off_macro);
+    hipError_t e = launch_macro(h, macro, nullptr, s);
+    if (e != hipSuccess) return e;
+    const uint64_t V = static_cast<uint64_t>(h->geo.N2) * h->geo.N;
+    return hipMemcpyAsync(dptr(h, h->L.off_snap), macro + V, 4 * V * sizeof(double),
+                          hipMemcpyDeviceToDevice, s);
+}
+
+Layout make_layout(int N, int storage) {
+    Layout L;
+    L.esize = storage == LBM_FP64 ? 8 : (storage == LBM_FP32 ? 4 : 2);
+    const uint64_t V = static_cast<uint64_t>(N) * N * N;
+    L.stride = (V + 511) / 512 * 512;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t o = 0;
+    L.off_pop = o;
+    o = up(o + kNPop * L.stride * L.esize);
+    L.off_macro = o;
+    o = up(o + 5 * V * sizeof(double));
+    L.off_snap = o;
+    o = up(o + 4 * V * sizeof(double));
+    L.off_wall = o;
+    o = up(o + 2 * static_cast<size_t>(N) * N * sizeof(double));
+    const uint64_t N2 = static_cast<uint64_t>(N) * N;
+    L.nblk_red = static_cast<uint32_t>((N2 + kRedBlock - 1) / kRedBlock * N);
+    L.off_part = o;
+    o = up(o + static_cast<size_t>(L.nblk_red) * kNPart * sizeof(double));
+    L.off_res = o;
+    o = up(o + kResDoubles * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+}  // namespace lbmk

@@ -1,0 +1,98 @@
+// lbm_internal.h -- shared between the kernels (kernels.hip) and the host API
+// (api.hip) of the gfx950 thermal lattice Boltzmann library.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+
+namespace lbmk {
+
+constexpr int kQF = 19;            // D3Q19 populations
+constexpr int kQG = 7;             // D3Q7 populations
+constexpr int kNPop = kQF + kQG;   // planes in device memory
+constexpr int kNPart = 24;         // doubles per block in the reduction scratch
+constexpr int kRedBlock = 256;     // threads per block of the reduction kernels
+constexpr int kMaxN = 1600;        // keeps N^2 * N below 2^32 (index arithmetic)
+
+// Relaxation and wall constants of one handle, in the arithmetic type R.
+template <class R>
+struct Coef {
+    R s_a;      // 1/tau_f: energy, its square, the stresses (Sec. 2.2)
+    R s_b;      // 8(2 tau_f - 1)/(8 tau_f - 1): energy fluxes, third-order moments
+    R q_k, q_e, q_nu, a_T;   // D3Q7 rates and a_T (Sec. 2.3)
+    R gbeta, T0;             // buoyancy g beta and reference temperature
+    R abb_hot, abb_cold;     // (6 + a_T)/21 * T_w of the hot and cold walls
+    R sf, isf;               // storage scale of f deviations and its inverse
+    R sg, isg;               // storage scale of g and its inverse
+};
+
+// Geometry of one launch: the grid is (ceil(N^2 / block), N); block b of
+// plane z covers in-plane indices r = b*block + t, with y = r / N.
+struct Geo {
+    int N;
+    uint32_t N2;
+    uint32_t magic;          // ceil(2^32 / N): y = umulhi(r, magic) for r < N^2
+    uint64_t stride;         // elements between population planes
+};
+
+struct Layout {
+    size_t esize = 0;        // bytes per stored population
+    uint64_t stride = 0;     // elements per population plane
+    size_t off_pop = 0, off_macro = 0, off_snap = 0, off_wall = 0;
+    size_t off_part = 0, off_res = 0, total = 0;
+    uint32_t nblk_red = 0;   // blocks of the node-parallel reduction kernels
+};
+
+Layout make_layout(int N, int storage);
+
+}  // namespace lbmk
+
+struct lbm {
+    lbm_params p{};
+    lbm_opts o{};
+    lbmk::Layout L{};
+    lbmk::Geo geo{};
+    int storage = 0;
+    int block = 256;
+    void *buf = nullptr;     // device buffer (caller's or ours)
+    bool own_buf = false;
+    int parity = 0;          // 0: planes hold f_i(x) in slot i; 1: post-collision swapped
+    int64_t t = 0;           // steps since set_fields
+    int64_t samples = 0;     // time-average samples taken
+    bool initialised = false;
+    bool has_flux = false;   // a step was taken since the populations were set
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    size_t events_used = 0;
+    std::string err;
+};
+
+namespace lbmk {
+
+// Launchers (kernels.hip).  All return the hipError_t of the launch.
+hipError_t launch_init(const lbm_t *h, const double *uvwT, hipStream_t s);
+hipError_t launch_set_pop(const lbm_t *h, const double *in, hipStream_t s);
+hipError_t launch_get_pop(const lbm_t *h, double *out, hipStream_t s);
+hipError_t launch_step(const lbm_t *h, int parity, hipStream_t s);
+hipError_t launch_macro(const lbm_t *h, double *macro_out, double *wall_out, hipStream_t s);
+// Reduces the macro planes (and wall fluxes) to the raw vector at res[0..];
+// with accumulate, also adds it to res[32..] and counts the sample.
+hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s);
+hipError_t launch_reset_acc(const lbm_t *h, hipStream_t s);
+// Residual against the snapshot into res[64..66], then snapshot := current.
+hipError_t launch_residual(const lbm_t *h, hipStream_t s);
+hipError_t launch_snapshot(const lbm_t *h, hipStream_t s);
+
+// Offsets (in doubles) of the result block.
+constexpr int kResCur = 0;
+constexpr int kResAcc = 32;   // LBM_NRAW sums, then the sample count
+constexpr int kResResid = 64;
+constexpr int kResDoubles = 96;
+
+}  // namespace lbmk

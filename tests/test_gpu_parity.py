@@ -1,0 +1,314 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Population tolerance (per population, after the stated number of steps):
+    |p_gpu - p_oracle| <= tol * max(|p_oracle|, floor_q)
+with floor_q = w_i for f and 0.5 * w^T_i for g (the size of a population at
+the largest |T| = 1/2), tol = 1e-5 for FP32 storage and arithmetic and 1e-12
+for FP64.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_08882_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+if not torch.cuda.is_available():  # collected on a CPU machine only with -m gpu
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1903_08882_amd import binding as B  # noqa: E402
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+CELL = {0: "side_heated", 1: "rayleigh_benard"}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
+
+
+def floors(p):
+    _, _, w = oracle.velocities19()
+    wT = np.array([p.wT0] + [p.wT1] * 6)
+    return np.concatenate([w, 0.5 * wT])
+
+
+def assert_pop_close(gpu, ora, p, tol, what=""):
+    gpu = np.asarray(gpu).reshape(26, -1)
+    ora = np.asarray(ora).reshape(26, -1)
+    bound = tol * np.maximum(np.abs(ora), floors(p)[:, None])
+    err = np.abs(gpu - ora)
+    bad = err > bound
+    if bad.any():
+        q, n = np.unravel_index(np.argmax(err / bound), err.shape)
+        raise AssertionError(f"{what}: {bad.sum()} populations off; worst q={q} node={n} "
+                             f"gpu={gpu[q, n]!r} oracle={ora[q, n]!r} ratio={err[q, n] / bound[q, n]:.3g}")
+
+
+class Pair:
+    """The same problem on the GPU and in the oracle."""
+
+    def __init__(self, N, Ra, Pr, cell, storage, U=0.1, T0=0.0, sample_every=0, block=0):
+        self.N, self.storage = N, storage
+        say(f"[pair] N={N} Ra={Ra} Pr={Pr} cell={CELL[cell]} storage={storage} U={U}")
+        self.h = B.lbm_create(N, Ra, Pr, cell, storage,
+                              B.lbm_default_opts(U=U, T0=T0, sample_every=sample_every, block=block))
+        self.o = oracle.Oracle(N, Ra, Pr, cell, U=U, T0=T0)
+        self.p = self.o.p
+
+    def init_rest_noise(self, seed=synth.SEED0):
+        f = synth.rest_with_noise(self.N, seed)
+        self.o.init_fields(f)
+        B.lbm_set_fields(self.h, dev(f))
+
+    def init_rich(self, seed=synth.SEED0 + 100):
+        rho, uvwT = synth.rich_fields(self.N, seed)
+        self.o.init_fields(uvwT, rho)
+        noise = synth.population_noise(self.N, seed).reshape(26, -1)
+        pop = self.o.pop + 1e-4 * floors(self.p)[:, None] * noise
+        self.o.set_populations(pop)
+        B.lbm_set_populations(self.h, dev(pop))
+
+    def step(self, n):
+        self.o.step(n)
+        B.lbm_step(self.h, n)
+
+    def gpu_pop(self):
+        return B.lbm_get_populations(self.h).cpu().numpy().reshape(26, -1)
+
+    def check_pop(self, what=""):
+        assert_pop_close(self.gpu_pop(), self.o.pop, self.p, TOL[self.storage], what)
+
+
+# --------------------------------------------------------------------------
+# Populations
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_side_heated_small_config_200_steps(storage):
+    """33^3 side-heated cell, Ra 1e4, Pr 0.71, U = 0.1, fluid at rest with
+    seeded +-1e-3 temperature noise; populations after 200 and 201 steps."""
+    pr = Pair(33, 1e4, 0.71, 0, storage)
+    pr.init_rest_noise()
+    pr.check_pop("t=0")
+    pr.step(200)
+    pr.check_pop("t=200")
+    pr.step(1)
+    pr.check_pop("t=201 (swapped storage)")
+
+
+@pytest.mark.parametrize("cell", [0, 1])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_rich_state_200_steps(cell, storage):
+    """A state exciting every moment (rho, u, T random; off-equilibrium
+    populations), N = 21 (ragged last block of each plane), both cells."""
+    pr = Pair(21, 1e5, 0.71, cell, storage, U=0.1)
+    pr.init_rich()
+    pr.check_pop("t=0")
+    pr.step(1)
+    pr.check_pop("t=1")
+    pr.step(199)
+    pr.check_pop("t=200")
+
+
+@pytest.mark.parametrize("N", [3, 4, 8])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_smallest_and_even_sizes(N, storage):
+    pr = Pair(N, 1e4, 7.0, 1, storage, U=0.1)
+    pr.init_rich()
+    pr.step(31)
+    pr.check_pop("t=31")
+    pr.step(20)
+    pr.check_pop("t=51")
+
+
+def test_rayleigh_benard_fp64_long_run_matches():
+    pr = Pair(16, 1e6, 0.7, 1, "fp64", U=0.1 / np.sqrt(3))
+    pr.init_rest_noise(seed=synth.SEED0 + 2)
+    pr.step(1000)
+    pr.check_pop("t=1000")
+
+
+def test_block_sizes_give_identical_results():
+    ref = None
+    for block in (64, 128, 192, 256):
+        h = B.lbm_create(23, 1e5, 0.71, 0, "fp32", B.lbm_default_opts(U=0.1, block=block))
+        rho, uvwT = synth.rich_fields(23)
+        B.lbm_set_fields(h, dev(uvwT))
+        B.lbm_step(h, 7)
+        pop = B.lbm_get_populations(h).cpu().numpy()
+        if ref is None:
+            ref = pop
+        else:
+            assert np.array_equal(pop, ref), block
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_set_get_populations_round_trip(storage):
+    N = 9
+    o = oracle.Oracle(N, 1e4, 0.71, 0, U=0.1)
+    rho, uvwT = synth.rich_fields(N)
+    o.init_fields(uvwT, rho)
+    h = B.lbm_create(N, 1e4, 0.71, 0, storage, B.lbm_default_opts(U=0.1))
+    B.lbm_set_populations(h, dev(o.pop))
+    got = B.lbm_get_populations(h).cpu().numpy().reshape(26, -1)
+    if storage == "fp64":
+        assert np.abs(got - o.pop).max() < 1e-16
+    else:
+        assert_pop_close(got, o.pop, o.p, 1e-7, "round trip")
+
+
+# --------------------------------------------------------------------------
+# Macroscopic fields, observables, residual, averages
+# --------------------------------------------------------------------------
+
+def _raw_close(gpu, ora, tol, floor):
+    gpu, ora = np.asarray(gpu), np.asarray(ora)
+    err = np.abs(gpu - ora)
+    bound = tol * np.maximum(np.abs(ora), floor)
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, [(B.RAW_NAMES[k], gpu[k], ora[k]) for k in bad]
+
+
+def _raw_floor(p):
+    """Natural scale of each raw entry for this problem (lattice units)."""
+    U, N = p.U, p.N
+    f = np.empty(B.NRAW)
+    f[0:4] = p.kappa / N          # wall heat flux
+    f[4:8] = 1.0 / N              # wall temperature gradient
+    f[8:10] = U * U               # <|u|^2>, <w^2>
+    f[10:12] = 0.5 * U            # <wT>, <uT>
+    f[12] = p.nu * (U / N) ** 2   # eps_u
+    f[13] = p.kappa / N ** 2      # eps_T
+    f[14] = 1e-6                  # <drho^2>
+    f[15] = 1e-2                  # <T>
+    f[16] = 1e-3                  # <drho>
+    f[17] = (U / N) ** 2          # <(div u)^2>
+    return f
+
+
+@pytest.mark.parametrize("cell", [0, 1])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_fields_and_observables(cell, storage):
+    pr = Pair(19, 1e5, 0.71, cell, storage, U=0.1)
+    pr.init_rich()
+    pr.step(37)
+    tol = 1e-11 if storage == "fp64" else 2e-5
+    mg = B.lbm_get_fields(pr.h).cpu().numpy().reshape(5, -1)
+    mo = pr.o.macro()
+    scale = np.array([1.0, 0.1, 0.1, 0.1, 0.5])[:, None]
+    assert (np.abs(mg - mo) <= tol * np.maximum(np.abs(mo), scale)).all()
+    rg = B.lbm_observables_raw(pr.h)
+    ro = pr.o.observables_raw()
+    _raw_close(rg, ro, tol * (10 if storage == "fp32" else 1), _raw_floor(pr.p))
+    Nu, Re, eu, eT = B.lbm_observables(pr.h)
+    nd = oracle.nondimensional(pr.p, ro)
+    assert abs(Nu - 0.5 * (nd["Nu_hot"] + nd["Nu_cold"])) <= 1e-3 * abs(nd["Nu_hot"]) + 1e-9
+    assert abs(Re - nd["Re_rms"]) <= 1e-4 * nd["Re_rms"]
+    assert abs(eu - nd["eps_u"]) <= 1e-4 * nd["eps_u"]
+    assert abs(eT - nd["eps_T"]) <= 1e-4 * nd["eps_T"]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_residual_against_oracle(storage):
+    pr = Pair(17, 1e5, 0.71, 0, storage, U=0.1)
+    pr.init_rich()
+    m0 = pr.o.macro()
+    pr.step(13)
+    got = B.lbm_residual(pr.h)
+    want = pr.o.residual(m0)
+    tol = 1e-10 if storage == "fp64" else 1e-4
+    for g, w in zip(got, want):
+        assert abs(g - w) <= tol * abs(w)
+    m1 = pr.o.macro()
+    pr.step(5)
+    got = B.lbm_residual(pr.h)         # against the state recorded by the last call
+    want = pr.o.residual(m1)
+    for g, w in zip(got, want):
+        assert abs(g - w) <= tol * abs(w)
+
+
+def test_time_averages_match_oracle_samples():
+    pr = Pair(15, 1e5, 0.71, 1, "fp64", U=0.1, sample_every=4)
+    pr.init_rich()
+    acc = np.zeros(B.NRAW)
+    for _ in range(5):
+        pr.step(4)
+        acc += pr.o.observables_raw()
+    mean, count = B.lbm_averages(pr.h)
+    assert count == 5
+    _raw_close(mean, acc / 5, 1e-11, _raw_floor(pr.p))
+    B.lbm_reset_averages(pr.h)
+    with pytest.raises(B.LBMError):
+        B.lbm_averages(pr.h)
+
+
+def test_mass_and_energy_balance_at_any_size():
+    """Sum of rho is conserved; the change of sum T over a step equals the heat
+    entering through the isothermal walls in that step (GPU only, FP64)."""
+    N = 65
+    h = B.lbm_create(N, 1e6, 0.71, 0, "fp64")
+    rho, uvwT = synth.rich_fields(N)
+    B.lbm_set_fields(h, dev(uvwT))
+    V, A = N ** 3, N * N
+    r0 = B.lbm_observables_raw(h)
+    for _ in range(3):
+        ra = B.lbm_observables_raw(h)
+        B.lbm_step(h, 1)
+        rb = B.lbm_observables_raw(h)
+        dE = (rb[15] - ra[15]) * V
+        assert abs(dE - (rb[0] + rb[1]) * A) < 1e-12 * A
+        assert abs(rb[16] - r0[16]) * V < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Error paths
+# --------------------------------------------------------------------------
+
+def test_errors_before_initialisation_and_on_divergence():
+    h = B.lbm_create(8, 1e4, 0.71, 0, "fp32", B.lbm_default_opts(U=0.1))
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_step(h, 1)
+    assert e.value.status == -6
+    o = oracle.Oracle(8, 1e4, 0.71, 0, U=0.1)
+    o.init_fields(synth.rest_with_noise(8))
+    pop = o.pop.copy()
+    pop[3, 100] = np.nan
+    B.lbm_set_populations(h, dev(pop))
+    B.lbm_step(h, 2)
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_observables_raw(h)
+    assert e.value.status == -5
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_residual(h)
+    assert e.value.status == -5
+
+
+# --------------------------------------------------------------------------
+# Full size, launch configuration of the benchmark
+# --------------------------------------------------------------------------
+
+def test_full_size_257_one_step_against_oracle():
+    """257^3 side-heated, Ra 1e7, FP32 storage and the default launch: the
+    canonical state after 3 steps is handed to the oracle, both take one step,
+    and every population is compared (one FP32 step: tolerance 1e-5)."""
+    N = 257
+    h = B.lbm_create(N, 1e7, 0.71, 0, "fp32")
+    B.lbm_set_fields(h, dev(synth.rest_with_noise(N)))
+    B.lbm_step(h, 3)
+    before = B.lbm_get_populations(h).cpu().numpy()
+    B.lbm_step(h, 1)
+    after = B.lbm_get_populations(h).cpu().numpy()
+    del h
+    torch.cuda.empty_cache()
+    o = oracle.Oracle(N, 1e7, 0.71, 0)
+    o.set_populations(before)
+    del before
+    o.step(1)
+    assert_pop_close(after, o.pop, o.p, 1e-5, "257^3 one step")

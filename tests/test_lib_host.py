@@ -1,0 +1,115 @@
+"""CPU tests of the HIP library's host side: it loads, exports every symbol
+that include/lbm.h declares, and its host-only calls (parameter derivation,
+state size, conversion to nondimensional numbers, argument checks) agree with
+the oracle.  No GPU call is made."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import ROOT
+
+torch = pytest.importorskip("torch")
+from paper_1903_08882_amd import binding as B  # noqa: E402
+
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^LBM_API[^(]*?\b(lbm_\w+)\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    lib = B.lib()
+    for s in syms:
+        assert hasattr(lib, s), s
+    # and the binding wraps each of them under the same name
+    for s in syms:
+        assert hasattr(B, s) or s in ("lbm_last_error", "lbm_strerror"), s
+
+
+def test_binding_signature_table_covers_header():
+    assert set(declared_symbols()) == set(B._SIG)
+
+
+@pytest.mark.parametrize("cfg", [(33, 1e4, 0.71, 0, 0.1), (129, 1e6, 0.71, 0, None),
+                                 (257, 1e7, 0.71, 0, None), (257, 3e6, 7.0, 1, None),
+                                 (65, 1e5, 7.0, 1, None)])
+def test_derived_parameters_agree_with_oracle(cfg):
+    N, Ra, Pr, cell, U = cfg
+    opts = B.lbm_default_opts(U=U)
+    p = B.lbm_derive_params(N, Ra, Pr, cell, "fp32", opts)
+    q = oracle.derive(N, Ra, Pr, cell, p.U)
+    for k in ("H", "dT", "nu", "kappa", "gbeta", "tau_f", "s_e", "s_q", "q_k", "q_e", "q_nu",
+              "a_T", "wT0", "wT1", "T_hot", "T_cold"):
+        assert abs(getattr(p, k) - getattr(q, k)) <= 1e-15 * max(1.0, abs(getattr(q, k))), k
+    if U is None:
+        assert abs(p.U - 0.1 / math.sqrt(3)) < 1e-16
+
+
+def test_parameter_errors():
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_derive_params(2, 1e4, 0.71)
+    assert e.value.status == -1
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_derive_params(33, 1e3, 0.71, opts=B.lbm_default_opts(U=0.1))
+    assert e.value.status == -2       # a_T > 1: negative D3Q7 rest weight
+    with pytest.raises(B.LBMError):
+        B.lbm_derive_params(33, -1.0, 0.71)
+    with pytest.raises(B.LBMError):
+        B.lbm_derive_params(33, 1e4, float("nan"))
+    with pytest.raises(B.LBMError):
+        B.lbm_derive_params(33, 1e4, 0.71, cell=7)
+    with pytest.raises(B.LBMError):
+        B.lbm_derive_params(33, 1e4, 0.71, storage=9)
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_derive_params(1601, 1e4, 0.71)
+    assert e.value.status == -2
+
+
+def test_state_bytes_cover_populations_and_scratch():
+    for N, st, es in [(33, "fp32", 4), (257, "fp32", 4), (257, "fp64", 8), (129, "fp16s", 2)]:
+        b = B.lbm_state_bytes(N, st)
+        pops = 26 * N ** 3 * es
+        scratch = (5 + 4) * N ** 3 * 8
+        assert pops + scratch <= b <= pops + scratch + 64 * N * N * 8 + (1 << 20)
+
+
+@pytest.mark.parametrize("cell", [0, 1])
+def test_nondimensional_conversion_agrees_with_oracle(cell):
+    rng = np.random.default_rng(11)
+    raw = rng.uniform(-1e-2, 1e-2, B.NRAW)
+    raw[[8, 9, 12, 13, 14, 17]] = np.abs(raw[[8, 9, 12, 13, 14, 17]])
+    p = B.lbm_derive_params(65, 1e6, 0.7, cell)
+    q = oracle.derive(65, 1e6, 0.7, cell)
+    got = B.lbm_nondimensional(p, raw)
+    want = oracle.nondimensional(q, raw)
+    for k, v in want.items():
+        assert abs(got[k] - v) <= 1e-13 * max(1.0, abs(v)), k
+
+
+def test_create_rejects_bad_buffers_without_touching_the_gpu():
+    lib = B.lib()
+    import ctypes
+    o = B.lbm_default_opts(U=0.1)
+    h = ctypes.c_void_p()
+    # misaligned caller buffer
+    rc = lib.lbm_create(33, 1e4, 0.71, 0, 1, ctypes.byref(o), ctypes.c_void_p(0x1001), 1 << 30,
+                        ctypes.byref(h))
+    assert rc == -1
+    # buffer too small
+    rc = lib.lbm_create(33, 1e4, 0.71, 0, 1, ctypes.byref(o), ctypes.c_void_p(0x100000), 1024,
+                        ctypes.byref(h))
+    assert rc == -3
+    # bad block size
+    o.block = 96
+    rc = lib.lbm_create(33, 1e4, 0.71, 0, 1, ctypes.byref(o), ctypes.c_void_p(0x100000), 1 << 30,
+                        ctypes.byref(h))
+    assert rc == -1
+    assert lib.lbm_strerror(-5) == b"non-finite result (diverged)"
