@@ -173,8 +173,8 @@ LBM_API int lbm_set_fields(lbm_t *h, const double *uvwT, void *stream);
 LBM_API int lbm_get_fields(lbm_t *h, double *out, void *stream);
 
 /* Replace the populations.  in: device FP64 array [26][N^3] of pre-collision
- * populations.  Keeps the step counter; resets the residual snapshot.  The
- * values are rounded to the storage type. */
+ * populations.  Keeps the step counter; resets the time averages and the
+ * residual snapshot.  The values are rounded to the storage type. */
 LBM_API int lbm_set_populations(lbm_t *h, const double *in, void *stream);
 
 /* Pre-collision populations of the current time step.  out: device FP64

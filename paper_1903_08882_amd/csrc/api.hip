@@ -133,7 +133,9 @@ int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opt
     h->geo.N = N;
     h->geo.N2 = static_cast<uint32_t>(N) * static_cast<uint32_t>(N);
     h->geo.magic = static_cast<uint32_t>((0x100000000ull + N - 1) / N);
-    h->geo.stride = L.stride;
+    h->geo.slab = static_cast<uint32_t>(L.slab);
+    h->geo.bbits = L.bbits;
+    h->geo.bmask = (1u << L.bbits) - 1u;
     if (dev_buf) {
         h->buf = dev_buf;
     } else {
@@ -150,8 +152,8 @@ int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opt
 
 int lbm_destroy(lbm_t *h) {
     if (!h) return LBM_EINVAL;
-    for (hipEvent_t ev : h->events) hipEventDestroy(ev);
-    if (h->own_buf) hipFree(h->buf);
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    if (h->own_buf) (void)hipFree(h->buf);
     delete h;
     return LBM_OK;
 }
@@ -195,6 +197,8 @@ int lbm_set_populations(lbm_t *h, const double *in, void *stream) {
     h->parity = 0;
     h->has_flux = false;
     h->initialised = true;
+    if ((e = lbmk::launch_reset_acc(h, s)) != hipSuccess) return hip_fail(h, e, "reset averages");
+    h->samples = 0;
     if ((e = lbmk::launch_snapshot(h, s)) != hipSuccess) return hip_fail(h, e, "snapshot");
     return LBM_OK;
 }

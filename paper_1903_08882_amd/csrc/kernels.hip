@@ -1,10 +1,19 @@
 // kernels.hip -- gfx950 kernels of the coupled D3Q19-MRT / D3Q7-MRT thermal
 // lattice Boltzmann step (Xu, Shi & Xi 2019, arXiv:1903.08882).
 //
-// Storage.  26 population planes (f_0..f_18, g_0..g_6), x fastest, one plane
-// every `stride` elements.  f is stored as the deviation f_i - w_i from the
-// rest equilibrium (rho = 1, u = 0), g as is (its rest equilibrium at the mean
-// wall temperature 0 is zero); FP16 storage scales both by a power of two.
+// Storage: z-slabs of node blocks.  Each z-plane of the lattice is one slab;
+// its N^2 nodes, numbered r = x + N y, are cut into sub-blocks of B = 2^b
+// consecutive nodes (B * element size = 32 KB), and the 26 populations of a
+// sub-block (f_0..f_18, g_0..g_6) are stored one after the other:
+//   slot q of node (x, y, z) = z * slab + (r >> b) * 26 B + q B + (r & (B-1)).
+// All nodes of one launch block share z, so z enters through a wave-uniform
+// base and a lane only carries a 32-bit byte offset.  (Keeping the 26 copies
+// of a node within 26 * 32 KB of each other, instead of one full-lattice
+// plane apart, is what lets the 52 access streams of a step run near copy
+// bandwidth on HBM.)
+// f is stored as the deviation f_i - w_i from the rest equilibrium (rho = 1,
+// u = 0), g as is (its rest equilibrium at the mean wall temperature 0 is
+// zero); FP16 storage scales f by a power of two.
 //
 // Streaming uses the in-place AA pattern, so each step reads and writes the
 // same 26 slots per node and the state needs one copy:
@@ -95,9 +104,45 @@ __device__ __forceinline__ bool down_out(int ex, int ey, int ez, const Node &d, 
     return (ex > 0 && d.x == N - 1) || (ex < 0 && d.x == 0) || (ey > 0 && d.y == N - 1) ||
            (ey < 0 && d.y == 0) || (ez > 0 && d.z == N - 1) || (ez < 0 && d.z == 0);
 }
-__device__ __forceinline__ int64_t link_offset(int ex, int ey, int ez, const Geo &g) {
-    return static_cast<int64_t>(ex) + static_cast<int64_t>(ey) * g.N +
-           static_cast<int64_t>(ez) * static_cast<int64_t>(g.N2);
+// The populations of one node as seen from its launch block: a wave-uniform
+// byte base at the start of slab z - 1 and the node's in-plane index r.  Every
+// slot a node touches (its own slab and slabs z +- 1) lies within
+// [0, 3 slab) elements of the base.
+template <class S>
+struct View {
+    const char *base;
+    int r;
+};
+
+template <class S>
+__device__ __forceinline__ View<S> view_of(const S *pop, const Geo &g, const Node &d) {
+    View<S> v;
+    v.base = reinterpret_cast<const char *>(pop) +
+             (static_cast<int64_t>(d.z) - 1) * static_cast<int64_t>(g.slab * sizeof(S));
+    v.r = d.x + d.y * g.N;
+    return v;
+}
+
+// Byte offset from the base of slot q of the node displaced by (dx, dy, dz).
+// For a displacement out of the box the value is meaningless and unused.
+template <class S>
+__device__ __forceinline__ uint32_t slot(const View<S> &v, const Geo &g, int q, int dx, int dy,
+                                         int dz) {
+    const int r = v.r + dx + dy * g.N;
+    const uint32_t e = static_cast<uint32_t>(dz + 1) * g.slab +
+                       static_cast<uint32_t>(r >> g.bbits) * (kNPop << g.bbits) +
+                       (static_cast<uint32_t>(q) << g.bbits) + static_cast<uint32_t>(r & g.bmask);
+    return e * static_cast<uint32_t>(sizeof(S));
+}
+
+// Population loads and stores at a byte offset from a uniform base.
+template <class S>
+__device__ __forceinline__ S ld(const View<S> &v, uint32_t off) {
+    return *reinterpret_cast<const S *>(v.base + off);
+}
+template <class S>
+__device__ __forceinline__ void st(const View<S> &v, uint32_t off, S x) {
+    *reinterpret_cast<S *>(const_cast<char *>(v.base) + off) = x;
 }
 
 // Component of D3Q7 link j along the isothermal axis (x side-heated, z RB).
@@ -116,30 +161,32 @@ __device__ __forceinline__ void gather(const typename C::S *__restrict__ pop, co
                                        const Node &d, const Coef<typename C::R> &c,
                                        typename C::R f[kQF], typename C::R h[kQG]) {
     using R = typename C::R;
+    using S = typename C::S;
+    const View<S> v = view_of(pop, g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         if constexpr (!SW) {
-            f[i] = dec<C>(pop[static_cast<uint64_t>(i) * g.stride + d.n], c.isf);
+            f[i] = dec<C>(ld(v, slot(v, g, i, 0, 0, 0)), c.isf);
         } else {
             const bool out = up_out(EX[i], EY[i], EZ[i], d, g.N);
-            const uint64_t idx = out ? d.n : d.n - link_offset(EX[i], EY[i], EZ[i], g);
-            const uint64_t q = out ? i : OPP[i];
-            f[i] = dec<C>(pop[q * g.stride + idx], c.isf);
+            const uint32_t off = out ? slot(v, g, i, 0, 0, 0)
+                                     : slot(v, g, OPP[i], -EX[i], -EY[i], -EZ[i]);
+            f[i] = dec<C>(ld(v, off), c.isf);
         }
     }
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         if constexpr (!SW) {
-            h[j] = dec<C>(pop[static_cast<uint64_t>(kQF + j) * g.stride + d.n], c.isg);
+            h[j] = dec<C>(ld(v, slot(v, g, kQF + j, 0, 0, 0)), c.isg);
         } else {
             const bool out = up_out(GX[j], GY[j], GZ[j], d, g.N);
-            const uint64_t idx = out ? d.n : d.n - link_offset(GX[j], GY[j], GZ[j], g);
-            const uint64_t q = kQF + (out ? j : GOPP[j]);
-            R v = dec<C>(pop[q * g.stride + idx], c.isg);
+            const uint32_t off = out ? slot(v, g, kQF + j, 0, 0, 0)
+                                     : slot(v, g, kQF + GOPP[j], -GX[j], -GY[j], -GZ[j]);
+            R x = dec<C>(ld(v, off), c.isg);
             const int comp = iso_comp<CELL>(j);
             // arrived through the wall at the upstream side: anti-bounce-back
-            if (comp != 0 && out) v = (comp > 0 ? c.abb_hot : c.abb_cold) - v;
-            h[j] = v;
+            if (comp != 0 && out) x = (comp > 0 ? c.abb_hot : c.abb_cold) - x;
+            h[j] = x;
         }
     }
 }
@@ -150,30 +197,32 @@ __device__ __forceinline__ void scatter(typename C::S *__restrict__ pop, const G
                                         const Node &d, const Coef<typename C::R> &c,
                                         const typename C::R f[kQF], const typename C::R h[kQG]) {
     using R = typename C::R;
+    using S = typename C::S;
+    const View<S> v = view_of(static_cast<const S *>(pop), g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         if constexpr (!SW) {
-            pop[static_cast<uint64_t>(OPP[i]) * g.stride + d.n] = enc<C>(f[i], c.sf);
+            st(v, slot(v, g, OPP[i], 0, 0, 0), enc<C>(f[i], c.sf));
         } else {
             const bool out = down_out(EX[i], EY[i], EZ[i], d, g.N);
-            const uint64_t idx = out ? d.n : d.n + link_offset(EX[i], EY[i], EZ[i], g);
-            const uint64_t q = out ? OPP[i] : i;
-            pop[q * g.stride + idx] = enc<C>(f[i], c.sf);
+            const uint32_t off = out ? slot(v, g, OPP[i], 0, 0, 0)
+                                     : slot(v, g, i, EX[i], EY[i], EZ[i]);
+            st(v, off, enc<C>(f[i], c.sf));
         }
     }
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         if constexpr (!SW) {
-            pop[static_cast<uint64_t>(kQF + GOPP[j]) * g.stride + d.n] = enc<C>(h[j], c.sg);
+            st(v, slot(v, g, kQF + GOPP[j], 0, 0, 0), enc<C>(h[j], c.sg));
         } else {
             const bool out = down_out(GX[j], GY[j], GZ[j], d, g.N);
-            const uint64_t idx = out ? d.n : d.n + link_offset(GX[j], GY[j], GZ[j], g);
-            const uint64_t q = kQF + (out ? GOPP[j] : j);
-            R v = h[j];
+            const uint32_t off = out ? slot(v, g, kQF + GOPP[j], 0, 0, 0)
+                                     : slot(v, g, kQF + j, GX[j], GY[j], GZ[j]);
+            R x = h[j];
             const int comp = iso_comp<CELL>(j);
             // leaves through the wall at the downstream side: anti-bounce-back
-            if (comp != 0 && out) v = (comp > 0 ? c.abb_cold : c.abb_hot) - v;
-            pop[q * g.stride + idx] = enc<C>(v, c.sg);
+            if (comp != 0 && out) x = (comp > 0 ? c.abb_cold : c.abb_hot) - x;
+            st(v, off, enc<C>(x, c.sg));
         }
     }
 }
@@ -369,20 +418,20 @@ __global__ __launch_bounds__(256) void k_init(typename C::S *__restrict__ pop, G
     const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
     const double u = uvwT[d.n], v = uvwT[V + d.n], w = uvwT[2 * V + d.n], T = uvwT[3 * V + d.n];
     const double uu = u * u + v * v + w * w;
+    using S = typename C::S;
+    const View<S> vw = view_of(static_cast<const S *>(pop), g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         const double eu = EX[i] * u + EY[i] * v + EZ[i] * w;
         const double fdev = wrest(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        pop[static_cast<uint64_t>(i) * g.stride + d.n] =
-            enc<C>(static_cast<typename C::R>(fdev), c.sf);
+        st(vw, slot(vw, g, i, 0, 0, 0), enc<C>(static_cast<typename C::R>(fdev), c.sf));
     }
     const double k = 21.0 / (6.0 + aT);
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         const double eu = GX[j] * u + GY[j] * v + GZ[j] * w;
         const double gv = (j == 0 ? wT0 : wT1) * T * (1.0 + k * eu);
-        pop[static_cast<uint64_t>(kQF + j) * g.stride + d.n] =
-            enc<C>(static_cast<typename C::R>(gv), c.sg);
+        st(vw, slot(vw, g, kQF + j, 0, 0, 0), enc<C>(static_cast<typename C::R>(gv), c.sg));
     }
 }
 
@@ -393,14 +442,16 @@ __global__ __launch_bounds__(256) void k_set_pop(typename C::S *__restrict__ pop
     Node d;
     if (!node_of(g, d)) return;
     const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+    using S = typename C::S;
+    const View<S> vw = view_of(static_cast<const S *>(pop), g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i)
-        pop[static_cast<uint64_t>(i) * g.stride + d.n] =
-            enc<C>(static_cast<typename C::R>(in[i * V + d.n] - wrest(i)), c.sf);
+        st(vw, slot(vw, g, i, 0, 0, 0),
+           enc<C>(static_cast<typename C::R>(in[i * V + d.n] - wrest(i)), c.sf));
 #pragma unroll
     for (int j = 0; j < kQG; ++j)
-        pop[static_cast<uint64_t>(kQF + j) * g.stride + d.n] =
-            enc<C>(static_cast<typename C::R>(in[(kQF + j) * V + d.n]), c.sg);
+        st(vw, slot(vw, g, kQF + j, 0, 0, 0),
+           enc<C>(static_cast<typename C::R>(in[(kQF + j) * V + d.n]), c.sg));
 }
 
 template <class C, int CELL, bool SW>
@@ -823,18 +874,25 @@ Layout make_layout(int N, int storage) {
     Layout L;
     L.esize = storage == LBM_FP64 ? 8 : (storage == LBM_FP32 ? 4 : 2);
     const uint64_t V = static_cast<uint64_t>(N) * N * N;
-    L.stride = (V + 511) / 512 * 512;
+    const uint64_t N2 = static_cast<uint64_t>(N) * N;
+    // sub-blocks of 32 KB per population, or one power of two covering the
+    // whole plane when that is smaller
+    L.bbits = 0;
+    while ((uint64_t{1} << L.bbits) * L.esize < 32768 && (uint64_t{1} << L.bbits) < N2) ++L.bbits;
+    const uint64_t B = uint64_t{1} << L.bbits;
+    const uint64_t nsub = (N2 + B - 1) / B;
+    L.slab = nsub * kNPop * B;
+    L.pop_elems = L.slab * N;
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     size_t o = 0;
     L.off_pop = o;
-    o = up(o + kNPop * L.stride * L.esize);
+    o = up(o + L.pop_elems * L.esize);
     L.off_macro = o;
     o = up(o + 5 * V * sizeof(double));
     L.off_snap = o;
     o = up(o + 4 * V * sizeof(double));
     L.off_wall = o;
-    o = up(o + 2 * static_cast<size_t>(N) * N * sizeof(double));
-    const uint64_t N2 = static_cast<uint64_t>(N) * N;
+    o = up(o + 2 * N2 * sizeof(double));
     L.nblk_red = static_cast<uint32_t>((N2 + kRedBlock - 1) / kRedBlock * N);
     L.off_part = o;
     o = up(o + static_cast<size_t>(L.nblk_red) * kNPart * sizeof(double));

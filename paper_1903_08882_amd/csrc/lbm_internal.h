@@ -38,12 +38,15 @@ struct Geo {
     int N;
     uint32_t N2;
     uint32_t magic;          // ceil(2^32 / N): y = umulhi(r, magic) for r < N^2
-    uint64_t stride;         // elements between population planes
+    uint32_t slab;           // storage elements per z-plane (all 26 populations)
+    uint32_t bbits, bmask;   // sub-block of 2^bbits nodes; bmask = 2^bbits - 1
 };
 
 struct Layout {
     size_t esize = 0;        // bytes per stored population
-    uint64_t stride = 0;     // elements per population plane
+    uint32_t bbits = 0;      // log2 of the nodes per sub-block
+    uint64_t slab = 0;       // storage elements per z-plane
+    uint64_t pop_elems = 0;  // storage elements of all populations
     size_t off_pop = 0, off_macro = 0, off_snap = 0, off_wall = 0;
     size_t off_part = 0, off_res = 0, total = 0;
     uint32_t nblk_red = 0;   // blocks of the node-parallel reduction kernels
