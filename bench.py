@@ -42,11 +42,23 @@ def parse():
     ap.add_argument("--sample-every", type=int, default=100)
     ap.add_argument("--residual-every", type=int, default=1000)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=3,
+    ap.add_argument("--cpu-steps", type=int, default=30,
                     help="oracle steps of the CPU baseline sample (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per step-kernel launch, if recorded")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """Hash of the kernel source: recorded traffic is valid for this source only."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("kernels.hip", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1903_08882_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(a):
@@ -120,9 +132,9 @@ def main():
     traffic = None
     if os.path.exists(a.traffic_json):
         tj = json.load(open(a.traffic_json))
-        key = f"{a.cell}:{N}:{a.storage}"
-        if key in tj:
-            traffic = tj[key]
+        rec = tj.get(f"{a.cell}:{N}:{a.storage}")
+        if rec and rec.get("kernel_source") == kernel_source_hash():
+            traffic = rec["bytes_per_launch"]
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -153,6 +165,15 @@ def main():
     }
     del h
     torch.cuda.empty_cache()
+    if a.calibrate_copy:
+        n = a.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 4 * n
+        del src, dst
     out["cpu_baseline"] = cpu_baseline(a) if a.cpu_steps > 0 else None
     print(json.dumps(out), flush=True)
 

@@ -85,9 +85,21 @@ struct Node {
     uint64_t n;
 };
 
+// Launches are one-dimensional, gx blocks per z-plane.  The hardware hands
+// consecutive workgroups to the XCDs in turn; they are renumbered so that
+// each XCD works through one contiguous range of node chunks: neighbouring
+// chunks share the cache lines of the neighbour-shifted accesses, and each
+// XCD has its own L2.
+constexpr uint32_t kXCD = 8;
+
 __device__ __forceinline__ bool node_of(const Geo &g, Node &d) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    d.z = blockIdx.y;
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    const uint32_t xcd = b % kXCD, idx = b / kXCD;
+    const uint32_t per = nb / kXCD, rem = nb % kXCD;
+    const uint32_t lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    const uint32_t z = lb / g.gx;
+    const uint32_t r = (lb - z * g.gx) * blockDim.x + threadIdx.x;
+    d.z = static_cast<int>(z);
     d.y = __umulhi(r, g.magic);
     d.x = static_cast<int>(r) - d.y * g.N;
     d.n = static_cast<uint64_t>(d.z) * g.N2 + r;
@@ -614,11 +626,31 @@ __global__ __launch_bounds__(kRedBlock) void k_observe(Geo g, ObsArgs a,
             v[LBM_RAW_GRAD_COLD_MID] = wm * gr;
         }
     }
-    const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+    const uint32_t b = blockIdx.x;
     block_reduce_to<LBM_NRAW, false>(v, part + static_cast<uint64_t>(b) * kNPart);
 }
 
-// Sum the block partials in a fixed order and scale to means.
+// First level of the partial reduction: block b folds rows [b*per, (b+1)*per)
+// of `in` into row b of `out`, in a fixed order (sum, or max for column 0
+// when MAX0).
+template <int K, bool MAX0>
+__global__ __launch_bounds__(kRedBlock) void k_fold_rows(const double *__restrict__ in,
+                                                         uint32_t nrows, uint32_t per,
+                                                         double *__restrict__ out) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    const uint32_t lo = blockIdx.x * per, hi = min(nrows, lo + per);
+    for (uint32_t b = lo + threadIdx.x; b < hi; b += kRedBlock)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double x = in[static_cast<uint64_t>(b) * kNPart + k];
+            v[k] = (MAX0 && k == 0) ? fmax(v[k], x) : v[k] + x;
+        }
+    block_reduce_to<K, MAX0>(v, out + static_cast<uint64_t>(blockIdx.x) * kNPart);
+}
+
+// Sum the folded rows in a fixed order and scale to means.
 __global__ __launch_bounds__(kRedBlock) void k_finalize_obs(const double *__restrict__ part,
                                                             uint32_t nblk, double inv_V,
                                                             double inv_A, double inv_L,
@@ -675,7 +707,7 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(Geo g, const double *__r
         v[3] = sqrt(s);
         v[4] = sqrt(so);
     }
-    const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+    const uint32_t b = blockIdx.x;
     block_reduce_to<5, true>(v, part + static_cast<uint64_t>(b) * kNPart);
 }
 
@@ -720,8 +752,14 @@ Coef<R> make_coef(const lbm_t *h) {
     return c;
 }
 
+Geo geo_for(const lbm_t *h, int block) {
+    Geo g = h->geo;
+    g.gx = (g.N2 + block - 1) / block;
+    return g;
+}
+
 dim3 grid_of(const lbm_t *h, int block) {
-    return dim3((h->geo.N2 + block - 1) / block, h->geo.N, 1);
+    return dim3(geo_for(h, block).gx * h->geo.N, 1, 1);
 }
 
 template <class C>
@@ -745,7 +783,7 @@ hipError_t with_codec(const lbm_t *h, F &&fn) {
 template <class C, int CELL, bool SW>
 void step_one(const lbm_t *h, hipStream_t s) {
     k_step<C, CELL, SW><<<grid_of(h, h->block), h->block, 0, s>>>(
-        pop_ptr<C>(h), h->geo, make_coef<typename C::R>(h));
+        pop_ptr<C>(h), geo_for(h, h->block), make_coef<typename C::R>(h));
 }
 
 }  // namespace
@@ -770,7 +808,7 @@ hipError_t launch_step(const lbm_t *h, int parity, hipStream_t s) {
 hipError_t launch_init(const lbm_t *h, const double *uvwT, hipStream_t s) {
     return with_codec(h, [&](auto cd) {
         using C = decltype(cd);
-        k_init<C><<<grid_of(h, 256), 256, 0, s>>>(pop_ptr<C>(h), h->geo,
+        k_init<C><<<grid_of(h, 256), 256, 0, s>>>(pop_ptr<C>(h), geo_for(h, 256),
                                                  make_coef<typename C::R>(h), uvwT, h->p.wT0,
                                                  h->p.wT1, h->p.a_T);
         return hipGetLastError();
@@ -780,7 +818,7 @@ hipError_t launch_init(const lbm_t *h, const double *uvwT, hipStream_t s) {
 hipError_t launch_set_pop(const lbm_t *h, const double *in, hipStream_t s) {
     return with_codec(h, [&](auto cd) {
         using C = decltype(cd);
-        k_set_pop<C><<<grid_of(h, 256), 256, 0, s>>>(pop_ptr<C>(h), h->geo,
+        k_set_pop<C><<<grid_of(h, 256), 256, 0, s>>>(pop_ptr<C>(h), geo_for(h, 256),
                                                     make_coef<typename C::R>(h), in);
         return hipGetLastError();
     });
@@ -793,11 +831,11 @@ hipError_t launch_get_pop(const lbm_t *h, double *out, hipStream_t s) {
         const dim3 gr = grid_of(h, 256);
         const typename C::S *p = pop_ptr<C>(h);
         if (h->p.cell == LBM_SIDE_HEATED) {
-            if (h->parity) k_get_pop<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, h->geo, c, out);
-            else k_get_pop<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, h->geo, c, out);
+            if (h->parity) k_get_pop<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, out);
+            else k_get_pop<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, out);
         } else {
-            if (h->parity) k_get_pop<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, h->geo, c, out);
-            else k_get_pop<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, h->geo, c, out);
+            if (h->parity) k_get_pop<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, out);
+            else k_get_pop<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, out);
         }
         return hipGetLastError();
     });
@@ -813,14 +851,14 @@ hipError_t launch_macro(const lbm_t *h, double *macro_out, double *wall_out, hip
         const typename C::S *p = pop_ptr<C>(h);
         if (h->p.cell == LBM_SIDE_HEATED) {
             if (h->parity)
-                k_macro<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+                k_macro<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
             else
-                k_macro<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+                k_macro<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
         } else {
             if (h->parity)
-                k_macro<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+                k_macro<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
             else
-                k_macro<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, h->geo, c, macro_out, wall_out, abb_hot, abb_cold);
+                k_macro<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
         }
         return hipGetLastError();
     });
@@ -835,13 +873,17 @@ hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s) {
     double *part = dptr(h, h->L.off_part);
     const dim3 gr = grid_of(h, kRedBlock);
     if (h->p.cell == LBM_SIDE_HEATED)
-        k_observe<LBM_SIDE_HEATED><<<gr, kRedBlock, 0, s>>>(h->geo, a, macro, wall, part);
+        k_observe<LBM_SIDE_HEATED><<<gr, kRedBlock, 0, s>>>(geo_for(h, kRedBlock), a, macro, wall, part);
     else
-        k_observe<LBM_RAYLEIGH_BENARD><<<gr, kRedBlock, 0, s>>>(h->geo, a, macro, wall, part);
+        k_observe<LBM_RAYLEIGH_BENARD><<<gr, kRedBlock, 0, s>>>(geo_for(h, kRedBlock), a, macro, wall, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const double N = h->geo.N;
-    k_finalize_obs<<<1, kRedBlock, 0, s>>>(part, h->L.nblk_red, 1.0 / (N * N * N), 1.0 / (N * N),
-                                           1.0 / N, dptr(h, h->L.off_res), accumulate ? 1 : 0);
+    double *fold = dptr(h, h->L.off_fold);
+    const uint32_t per = (h->L.nblk_red + kFold - 1) / kFold;
+    k_fold_rows<LBM_NRAW, false><<<kFold, kRedBlock, 0, s>>>(part, h->L.nblk_red, per, fold);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_finalize_obs<<<1, kRedBlock, 0, s>>>(fold, kFold, 1.0 / (N * N * N), 1.0 / (N * N), 1.0 / N,
+                                           dptr(h, h->L.off_res), accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -855,9 +897,13 @@ hipError_t launch_residual(const lbm_t *h, hipStream_t s) {
     hipError_t e = launch_macro(h, macro, nullptr, s);
     if (e != hipSuccess) return e;
     double *part = dptr(h, h->L.off_part);
-    k_residual<<<grid_of(h, kRedBlock), kRedBlock, 0, s>>>(h->geo, macro, dptr(h, h->L.off_snap), part);
+    k_residual<<<grid_of(h, kRedBlock), kRedBlock, 0, s>>>(geo_for(h, kRedBlock), macro, dptr(h, h->L.off_snap), part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_finalize_residual<<<1, kRedBlock, 0, s>>>(part, h->L.nblk_red, dptr(h, h->L.off_res));
+    double *fold = dptr(h, h->L.off_fold);
+    const uint32_t per = (h->L.nblk_red + kFold - 1) / kFold;
+    k_fold_rows<5, true><<<kFold, kRedBlock, 0, s>>>(part, h->L.nblk_red, per, fold);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_finalize_residual<<<1, kRedBlock, 0, s>>>(fold, kFold, dptr(h, h->L.off_res));
     return hipGetLastError();
 }
 
@@ -896,6 +942,8 @@ Layout make_layout(int N, int storage) {
     L.nblk_red = static_cast<uint32_t>((N2 + kRedBlock - 1) / kRedBlock * N);
     L.off_part = o;
     o = up(o + static_cast<size_t>(L.nblk_red) * kNPart * sizeof(double));
+    L.off_fold = o;
+    o = up(o + static_cast<size_t>(kFold) * kNPart * sizeof(double));
     L.off_res = o;
     o = up(o + kResDoubles * sizeof(double));
     L.total = o;

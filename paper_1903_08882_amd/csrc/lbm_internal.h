@@ -18,6 +18,7 @@ constexpr int kQG = 7;             // D3Q7 populations
 constexpr int kNPop = kQF + kQG;   // planes in device memory
 constexpr int kNPart = 24;         // doubles per block in the reduction scratch
 constexpr int kRedBlock = 256;     // threads per block of the reduction kernels
+constexpr uint32_t kFold = 256;    // blocks of the first reduction level
 constexpr int kMaxN = 1600;        // keeps N^2 * N below 2^32 (index arithmetic)
 
 // Relaxation and wall constants of one handle, in the arithmetic type R.
@@ -32,11 +33,13 @@ struct Coef {
     R sg, isg;               // storage scale of g and its inverse
 };
 
-// Geometry of one launch: the grid is (ceil(N^2 / block), N); block b of
-// plane z covers in-plane indices r = b*block + t, with y = r / N.
+// Geometry of one launch: gx = ceil(N^2 / block) blocks per z-plane, gx * N
+// blocks in all; block b of plane z covers in-plane indices r = b*block + t,
+// with y = r / N.
 struct Geo {
     int N;
     uint32_t N2;
+    uint32_t gx;
     uint32_t magic;          // ceil(2^32 / N): y = umulhi(r, magic) for r < N^2
     uint32_t slab;           // storage elements per z-plane (all 26 populations)
     uint32_t bbits, bmask;   // sub-block of 2^bbits nodes; bmask = 2^bbits - 1
@@ -48,7 +51,7 @@ struct Layout {
     uint64_t slab = 0;       // storage elements per z-plane
     uint64_t pop_elems = 0;  // storage elements of all populations
     size_t off_pop = 0, off_macro = 0, off_snap = 0, off_wall = 0;
-    size_t off_part = 0, off_res = 0, total = 0;
+    size_t off_part = 0, off_fold = 0, off_res = 0, total = 0;
     uint32_t nblk_red = 0;   // blocks of the node-parallel reduction kernels
 };
 
