@@ -25,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 METRIC = "coupled-lattice MLUPS & % HBM roofline; steps-to-steady vs plain at Nu ±0.5%"
-BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16s": 2}
+# bytes of one node's 26 populations in HBM (FP16 storage keeps the resting
+# thermal population g_0 in FP32); a step reads and writes each once
+NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 25 * 2 + 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage / f32 compute"}
 
 
@@ -126,7 +128,7 @@ def main():
 
     V = N ** 3
     mlups = V * a.steps / elapsed / 1e6
-    bytes_step = 2 * 26 * BYTES_PER_POP[a.storage] * V
+    bytes_step = 2 * NODE_BYTES[a.storage] * V
     avg_kernel_s = kernel_ms / 1e3 / max(kernels, 1)
     achieved = bytes_step / avg_kernel_s / 1e9
     traffic = None

@@ -134,6 +134,7 @@ int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opt
     h->geo.N2 = static_cast<uint32_t>(N) * static_cast<uint32_t>(N);
     h->geo.magic = static_cast<uint32_t>((0x100000000ull + N - 1) / N);
     h->geo.slab = static_cast<uint32_t>(L.slab);
+    h->geo.sub = static_cast<uint32_t>(L.sub);
     h->geo.bbits = L.bbits;
     h->geo.bmask = (1u << L.bbits) - 1u;
     if (dev_buf) {

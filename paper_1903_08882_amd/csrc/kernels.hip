@@ -5,15 +5,19 @@
 // its N^2 nodes, numbered r = x + N y, are cut into sub-blocks of B = 2^b
 // consecutive nodes (B * element size = 32 KB), and the 26 populations of a
 // sub-block (f_0..f_18, g_0..g_6) are stored one after the other:
-//   slot q of node (x, y, z) = z * slab + (r >> b) * 26 B + q B + (r & (B-1)).
-// All nodes of one launch block share z, so z enters through a wave-uniform
-// base and a lane only carries a 32-bit byte offset.  (Keeping the 26 copies
-// of a node within 26 * 32 KB of each other, instead of one full-lattice
-// plane apart, is what lets the 52 access streams of a step run near copy
-// bandwidth on HBM.)
+//   slot q of node (x, y, z) at byte
+//     z slab + (r >> b) sub + start(q) B + (r & (B-1)) size(q),
+// where size(q) is the storage width of population q and start(q) the sum of
+// the widths before it.  All nodes of one launch block share z, so z enters
+// through a wave-uniform base and a lane only carries a 32-bit byte offset.
+// (Keeping the 26 copies of a node within one sub-block, instead of one
+// full-lattice plane apart, is what lets the 52 access streams of a step run
+// near copy bandwidth on HBM.)
 // f is stored as the deviation f_i - w_i from the rest equilibrium (rho = 1,
 // u = 0), g as is (its rest equilibrium at the mean wall temperature 0 is
-// zero); FP16 storage scales f by a power of two.
+// zero).  FP16 storage scales the moving populations by a power of two and
+// keeps the resting thermal population g_0 (about w_0^T T, up to 0.47) in
+// FP32: resting populations never move, so their width is free to choose.
 //
 // Streaming uses the in-place AA pattern, so each step reads and writes the
 // same 26 slots per node and the state needs one copy:
@@ -58,9 +62,23 @@ __host__ __device__ constexpr double wrest(int i) {
 // ---------------------------------------------------------------------------
 // Storage codecs
 // ---------------------------------------------------------------------------
-struct CF64 { using S = double; using R = double; };
-struct CF32 { using S = float; using R = float; };
-struct CF16 { using S = _Float16; using R = float; };
+// S: storage type of a moving population, W: of the resting thermal
+// population g_0, R: arithmetic type.
+struct CF64 { using S = double; using W = double; using R = double; };
+struct CF32 { using S = float; using W = float; using R = float; };
+struct CF16 { using S = _Float16; using W = float; using R = float; };
+
+// Storage width and byte start (per node of a sub-block) of population q.
+template <class C>
+__host__ __device__ constexpr uint32_t qsize(int q) {
+    return q == kQF ? sizeof(typename C::W) : sizeof(typename C::S);
+}
+template <class C>
+__host__ __device__ constexpr uint32_t qstart(int q) {
+    return q <= kQF ? q * sizeof(typename C::S)
+                    : kQF * sizeof(typename C::S) + sizeof(typename C::W) +
+                          (q - kQF - 1) * sizeof(typename C::S);
+}
 
 template <class C>
 __device__ __forceinline__ typename C::R dec(typename C::S v, typename C::R inv_scale) {
@@ -119,42 +137,53 @@ __device__ __forceinline__ bool down_out(int ex, int ey, int ez, const Node &d, 
 // The populations of one node as seen from its launch block: a wave-uniform
 // byte base at the start of slab z - 1 and the node's in-plane index r.  Every
 // slot a node touches (its own slab and slabs z +- 1) lies within
-// [0, 3 slab) elements of the base.
-template <class S>
+// [0, 3 slab) bytes of the base.
 struct View {
     const char *base;
     int r;
 };
 
-template <class S>
-__device__ __forceinline__ View<S> view_of(const S *pop, const Geo &g, const Node &d) {
-    View<S> v;
-    v.base = reinterpret_cast<const char *>(pop) +
-             (static_cast<int64_t>(d.z) - 1) * static_cast<int64_t>(g.slab * sizeof(S));
+__device__ __forceinline__ View view_of(const void *pop, const Geo &g, const Node &d) {
+    View v;
+    v.base = static_cast<const char *>(pop) +
+             (static_cast<int64_t>(d.z) - 1) * static_cast<int64_t>(g.slab);
     v.r = d.x + d.y * g.N;
     return v;
 }
 
 // Byte offset from the base of slot q of the node displaced by (dx, dy, dz).
 // For a displacement out of the box the value is meaningless and unused.
-template <class S>
-__device__ __forceinline__ uint32_t slot(const View<S> &v, const Geo &g, int q, int dx, int dy,
+template <class C>
+__device__ __forceinline__ uint32_t slot(const View &v, const Geo &g, int q, int dx, int dy,
                                          int dz) {
     const int r = v.r + dx + dy * g.N;
-    const uint32_t e = static_cast<uint32_t>(dz + 1) * g.slab +
-                       static_cast<uint32_t>(r >> g.bbits) * (kNPop << g.bbits) +
-                       (static_cast<uint32_t>(q) << g.bbits) + static_cast<uint32_t>(r & g.bmask);
-    return e * static_cast<uint32_t>(sizeof(S));
+    return static_cast<uint32_t>(dz + 1) * g.slab + static_cast<uint32_t>(r >> g.bbits) * g.sub +
+           (qstart<C>(q) << g.bbits) + static_cast<uint32_t>(r & g.bmask) * qsize<C>(q);
 }
 
-// Population loads and stores at a byte offset from a uniform base.
-template <class S>
-__device__ __forceinline__ S ld(const View<S> &v, uint32_t off) {
-    return *reinterpret_cast<const S *>(v.base + off);
+// Loads and stores of f (moving), g_j for j >= 1 (moving) and g_0 (resting).
+template <class C>
+__device__ __forceinline__ typename C::R ld_f(const View &v, uint32_t off,
+                                              const Coef<typename C::R> &c) {
+    return dec<C>(*reinterpret_cast<const typename C::S *>(v.base + off), c.isf);
 }
-template <class S>
-__device__ __forceinline__ void st(const View<S> &v, uint32_t off, S x) {
-    *reinterpret_cast<S *>(const_cast<char *>(v.base) + off) = x;
+template <class C>
+__device__ __forceinline__ typename C::R ld_g(const View &v, uint32_t off, int j,
+                                              const Coef<typename C::R> &c) {
+    if (j == 0) return static_cast<typename C::R>(*reinterpret_cast<const typename C::W *>(v.base + off));
+    return dec<C>(*reinterpret_cast<const typename C::S *>(v.base + off), c.isg);
+}
+template <class C>
+__device__ __forceinline__ void st_f(const View &v, uint32_t off, typename C::R x,
+                                     const Coef<typename C::R> &c) {
+    *reinterpret_cast<typename C::S *>(const_cast<char *>(v.base) + off) = enc<C>(x, c.sf);
+}
+template <class C>
+__device__ __forceinline__ void st_g(const View &v, uint32_t off, int j, typename C::R x,
+                                     const Coef<typename C::R> &c) {
+    char *p = const_cast<char *>(v.base) + off;
+    if (j == 0) *reinterpret_cast<typename C::W *>(p) = static_cast<typename C::W>(x);
+    else *reinterpret_cast<typename C::S *>(p) = enc<C>(x, c.sg);
 }
 
 // Component of D3Q7 link j along the isothermal axis (x side-heated, z RB).
@@ -173,28 +202,27 @@ __device__ __forceinline__ void gather(const typename C::S *__restrict__ pop, co
                                        const Node &d, const Coef<typename C::R> &c,
                                        typename C::R f[kQF], typename C::R h[kQG]) {
     using R = typename C::R;
-    using S = typename C::S;
-    const View<S> v = view_of(pop, g, d);
+    const View v = view_of(pop, g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         if constexpr (!SW) {
-            f[i] = dec<C>(ld(v, slot(v, g, i, 0, 0, 0)), c.isf);
+            f[i] = ld_f<C>(v, slot<C>(v, g, i, 0, 0, 0), c);
         } else {
             const bool out = up_out(EX[i], EY[i], EZ[i], d, g.N);
-            const uint32_t off = out ? slot(v, g, i, 0, 0, 0)
-                                     : slot(v, g, OPP[i], -EX[i], -EY[i], -EZ[i]);
-            f[i] = dec<C>(ld(v, off), c.isf);
+            const uint32_t off = out ? slot<C>(v, g, i, 0, 0, 0)
+                                     : slot<C>(v, g, OPP[i], -EX[i], -EY[i], -EZ[i]);
+            f[i] = ld_f<C>(v, off, c);
         }
     }
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         if constexpr (!SW) {
-            h[j] = dec<C>(ld(v, slot(v, g, kQF + j, 0, 0, 0)), c.isg);
+            h[j] = ld_g<C>(v, slot<C>(v, g, kQF + j, 0, 0, 0), j, c);
         } else {
             const bool out = up_out(GX[j], GY[j], GZ[j], d, g.N);
-            const uint32_t off = out ? slot(v, g, kQF + j, 0, 0, 0)
-                                     : slot(v, g, kQF + GOPP[j], -GX[j], -GY[j], -GZ[j]);
-            R x = dec<C>(ld(v, off), c.isg);
+            const uint32_t off = out ? slot<C>(v, g, kQF + j, 0, 0, 0)
+                                     : slot<C>(v, g, kQF + GOPP[j], -GX[j], -GY[j], -GZ[j]);
+            R x = ld_g<C>(v, off, j, c);
             const int comp = iso_comp<CELL>(j);
             // arrived through the wall at the upstream side: anti-bounce-back
             if (comp != 0 && out) x = (comp > 0 ? c.abb_hot : c.abb_cold) - x;
@@ -209,32 +237,31 @@ __device__ __forceinline__ void scatter(typename C::S *__restrict__ pop, const G
                                         const Node &d, const Coef<typename C::R> &c,
                                         const typename C::R f[kQF], const typename C::R h[kQG]) {
     using R = typename C::R;
-    using S = typename C::S;
-    const View<S> v = view_of(static_cast<const S *>(pop), g, d);
+    const View v = view_of(pop, g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         if constexpr (!SW) {
-            st(v, slot(v, g, OPP[i], 0, 0, 0), enc<C>(f[i], c.sf));
+            st_f<C>(v, slot<C>(v, g, OPP[i], 0, 0, 0), f[i], c);
         } else {
             const bool out = down_out(EX[i], EY[i], EZ[i], d, g.N);
-            const uint32_t off = out ? slot(v, g, OPP[i], 0, 0, 0)
-                                     : slot(v, g, i, EX[i], EY[i], EZ[i]);
-            st(v, off, enc<C>(f[i], c.sf));
+            const uint32_t off = out ? slot<C>(v, g, OPP[i], 0, 0, 0)
+                                     : slot<C>(v, g, i, EX[i], EY[i], EZ[i]);
+            st_f<C>(v, off, f[i], c);
         }
     }
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         if constexpr (!SW) {
-            st(v, slot(v, g, kQF + GOPP[j], 0, 0, 0), enc<C>(h[j], c.sg));
+            st_g<C>(v, slot<C>(v, g, kQF + GOPP[j], 0, 0, 0), j, h[j], c);
         } else {
             const bool out = down_out(GX[j], GY[j], GZ[j], d, g.N);
-            const uint32_t off = out ? slot(v, g, kQF + GOPP[j], 0, 0, 0)
-                                     : slot(v, g, kQF + j, GX[j], GY[j], GZ[j]);
+            const uint32_t off = out ? slot<C>(v, g, kQF + GOPP[j], 0, 0, 0)
+                                     : slot<C>(v, g, kQF + j, GX[j], GY[j], GZ[j]);
             R x = h[j];
             const int comp = iso_comp<CELL>(j);
             // leaves through the wall at the downstream side: anti-bounce-back
             if (comp != 0 && out) x = (comp > 0 ? c.abb_cold : c.abb_hot) - x;
-            st(v, off, enc<C>(x, c.sg));
+            st_g<C>(v, off, j, x, c);
         }
     }
 }
@@ -430,20 +457,20 @@ __global__ __launch_bounds__(256) void k_init(typename C::S *__restrict__ pop, G
     const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
     const double u = uvwT[d.n], v = uvwT[V + d.n], w = uvwT[2 * V + d.n], T = uvwT[3 * V + d.n];
     const double uu = u * u + v * v + w * w;
-    using S = typename C::S;
-    const View<S> vw = view_of(static_cast<const S *>(pop), g, d);
+    using R = typename C::R;
+    const View vw = view_of(pop, g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         const double eu = EX[i] * u + EY[i] * v + EZ[i] * w;
         const double fdev = wrest(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        st(vw, slot(vw, g, i, 0, 0, 0), enc<C>(static_cast<typename C::R>(fdev), c.sf));
+        st_f<C>(vw, slot<C>(vw, g, i, 0, 0, 0), static_cast<R>(fdev), c);
     }
     const double k = 21.0 / (6.0 + aT);
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         const double eu = GX[j] * u + GY[j] * v + GZ[j] * w;
         const double gv = (j == 0 ? wT0 : wT1) * T * (1.0 + k * eu);
-        st(vw, slot(vw, g, kQF + j, 0, 0, 0), enc<C>(static_cast<typename C::R>(gv), c.sg));
+        st_g<C>(vw, slot<C>(vw, g, kQF + j, 0, 0, 0), j, static_cast<R>(gv), c);
     }
 }
 
@@ -454,16 +481,14 @@ __global__ __launch_bounds__(256) void k_set_pop(typename C::S *__restrict__ pop
     Node d;
     if (!node_of(g, d)) return;
     const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
-    using S = typename C::S;
-    const View<S> vw = view_of(static_cast<const S *>(pop), g, d);
+    using R = typename C::R;
+    const View vw = view_of(pop, g, d);
 #pragma unroll
     for (int i = 0; i < kQF; ++i)
-        st(vw, slot(vw, g, i, 0, 0, 0),
-           enc<C>(static_cast<typename C::R>(in[i * V + d.n] - wrest(i)), c.sf));
+        st_f<C>(vw, slot<C>(vw, g, i, 0, 0, 0), static_cast<R>(in[i * V + d.n] - wrest(i)), c);
 #pragma unroll
     for (int j = 0; j < kQG; ++j)
-        st(vw, slot(vw, g, kQF + j, 0, 0, 0),
-           enc<C>(static_cast<typename C::R>(in[(kQF + j) * V + d.n]), c.sg));
+        st_g<C>(vw, slot<C>(vw, g, kQF + j, 0, 0, 0), j, static_cast<R>(in[(kQF + j) * V + d.n]), c);
 }
 
 template <class C, int CELL, bool SW>
@@ -921,18 +946,21 @@ Layout make_layout(int N, int storage) {
     L.esize = storage == LBM_FP64 ? 8 : (storage == LBM_FP32 ? 4 : 2);
     const uint64_t V = static_cast<uint64_t>(N) * N * N;
     const uint64_t N2 = static_cast<uint64_t>(N) * N;
-    // sub-blocks of 32 KB per population, or one power of two covering the
-    // whole plane when that is smaller
+    // sub-blocks of 32 KB per (moving) population, or one power of two
+    // covering the whole plane when that is smaller
+    const uint64_t wide = storage == LBM_FP64 ? 8 : 4;   // width of the resting g_0
     L.bbits = 0;
     while ((uint64_t{1} << L.bbits) * L.esize < 32768 && (uint64_t{1} << L.bbits) < N2) ++L.bbits;
     const uint64_t B = uint64_t{1} << L.bbits;
     const uint64_t nsub = (N2 + B - 1) / B;
-    L.slab = nsub * kNPop * B;
-    L.pop_elems = L.slab * N;
+    L.node_bytes = (kNPop - 1) * L.esize + wide;
+    L.sub = L.node_bytes * B;
+    L.slab = nsub * L.sub;
+    L.pop_bytes = L.slab * N;
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     size_t o = 0;
     L.off_pop = o;
-    o = up(o + L.pop_elems * L.esize);
+    o = up(o + L.pop_bytes);
     L.off_macro = o;
     o = up(o + 5 * V * sizeof(double));
     L.off_snap = o;

@@ -41,15 +41,18 @@ struct Geo {
     uint32_t N2;
     uint32_t gx;
     uint32_t magic;          // ceil(2^32 / N): y = umulhi(r, magic) for r < N^2
-    uint32_t slab;           // storage elements per z-plane (all 26 populations)
+    uint32_t slab;           // storage bytes per z-plane (all 26 populations)
+    uint32_t sub;            // storage bytes per sub-block
     uint32_t bbits, bmask;   // sub-block of 2^bbits nodes; bmask = 2^bbits - 1
 };
 
 struct Layout {
-    size_t esize = 0;        // bytes per stored population
+    size_t esize = 0;        // bytes per stored moving population
+    uint64_t node_bytes = 0; // storage bytes of one node's 26 populations
     uint32_t bbits = 0;      // log2 of the nodes per sub-block
-    uint64_t slab = 0;       // storage elements per z-plane
-    uint64_t pop_elems = 0;  // storage elements of all populations
+    uint64_t sub = 0;        // storage bytes per sub-block
+    uint64_t slab = 0;       // storage bytes per z-plane
+    uint64_t pop_bytes = 0;  // storage bytes of all populations
     size_t off_pop = 0, off_macro = 0, off_snap = 0, off_wall = 0;
     size_t off_part = 0, off_fold = 0, off_res = 0, total = 0;
     uint32_t nblk_red = 0;   // blocks of the node-parallel reduction kernels
