@@ -220,6 +220,24 @@ LBM_API int lbm_reset_averages(lbm_t *h, void *stream);
 LBM_API int lbm_residual(lbm_t *h, void *stream, double *max_dT, double *rel_L1_T,
                  double *rel_L2_u);
 
+/* Steady-state driver (Sec. 3 criterion, with the maximum change of T as the
+ * stopping measure): repeat { lbm_step(check_every); lbm_residual } until
+ * max |T - T_old| < tol_max_dT or max_steps steps have been taken.  Writes the
+ * steps taken, the last max_dT and, when history != NULL, up to history_len
+ * max_dT values (one per check).  Returns LBM_OK whether or not it converged
+ * (compare *final_max_dT with tol_max_dT); errors as lbm_step/lbm_residual. */
+LBM_API int lbm_run_to_steady(lbm_t *h, int64_t check_every, double tol_max_dT,
+                              int64_t max_steps, void *stream, int64_t *steps_taken,
+                              double *final_max_dT, double *history, int64_t history_len);
+
+/* Mid-plane centreline maxima of the side-heated benchmark (Sec. 3, Table 1),
+ * in this library's axes (hot wall x = 0): out[0] = max u/U on the vertical
+ * line x = y = 1/2 and out[1] its height z/H; out[2] = max w/U on the
+ * horizontal line y = z = 1/2 and out[3] its position x/H; out[4] = E =
+ * <|u|^2>/(2 U^2).  Nodal values at (i + 1/2)/N; for even N the two central
+ * lines are averaged.  Synchronises stream. */
+LBM_API int lbm_centerline_peaks(lbm_t *h, void *stream, double out[5]);
+
 /* Kernel timing.  With profiling enabled, lbm_step brackets every step
  * kernel it launches with a pair of HIP events on its stream.
  * lbm_profile_read synchronises, returns the summed duration (ms) and number

@@ -83,6 +83,9 @@ _SIG = {
     "lbm_averages": (ctypes.c_int, [_P, _P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_reset_averages": (ctypes.c_int, [_P, _P]),
     "lbm_residual": (ctypes.c_int, [_P, _P, _D, _D, _D]),
+    "lbm_run_to_steady": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, _P,
+                                         ctypes.POINTER(ctypes.c_int64), _D, _D, ctypes.c_int64]),
+    "lbm_centerline_peaks": (ctypes.c_int, [_P, _P, _D]),
     "lbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "lbm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
@@ -260,6 +263,26 @@ def lbm_residual(h, stream=None):
     v = [ctypes.c_double() for _ in range(3)]
     _check(lib().lbm_residual(h.ptr, _stream(stream), *[ctypes.byref(x) for x in v]), h.ptr)
     return tuple(x.value for x in v)
+
+
+def lbm_run_to_steady(h, check_every=1000, tol_max_dT=1e-8, max_steps=10**6, stream=None,
+                      history_len=0):
+    """(steps taken, final max |dT|, residual history) of the steady-state loop."""
+    steps = ctypes.c_int64()
+    r = ctypes.c_double()
+    hist = (ctypes.c_double * max(history_len, 1))()
+    _check(lib().lbm_run_to_steady(h.ptr, int(check_every), float(tol_max_dT), int(max_steps),
+                                   _stream(stream), ctypes.byref(steps), ctypes.byref(r),
+                                   hist if history_len else None, int(history_len)), h.ptr)
+    nchk = -(-steps.value // int(check_every))
+    return steps.value, r.value, list(hist)[:min(history_len, nchk)]
+
+
+def lbm_centerline_peaks(h, stream=None):
+    """dict: u_max, z of u_max, w_max, x of w_max (nondimensional), E."""
+    out = (ctypes.c_double * 5)()
+    _check(lib().lbm_centerline_peaks(h.ptr, _stream(stream), out), h.ptr)
+    return dict(zip(["u_max", "u_max_z", "w_max", "w_max_x", "E"], list(out)))
 
 
 def lbm_profile(h, enable=True):

@@ -342,6 +342,51 @@ int lbm_residual(lbm_t *h, void *stream, double *max_dT, double *rel_L1_T, doubl
     return LBM_OK;
 }
 
+int lbm_run_to_steady(lbm_t *h, int64_t check_every, double tol_max_dT, int64_t max_steps,
+                      void *stream, int64_t *steps_taken, double *final_max_dT, double *history,
+                      int64_t history_len) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (check_every <= 0 || max_steps < 0 || !(tol_max_dT >= 0.0))
+        return fail(h, LBM_EINVAL, "bad check interval, step limit or tolerance");
+    int64_t done = 0, checks = 0;
+    double r = INFINITY;
+    while (done < max_steps) {
+        const int64_t k = check_every < max_steps - done ? check_every : max_steps - done;
+        if ((rc = lbm_step(h, k, stream)) != LBM_OK) return rc;
+        done += k;
+        if ((rc = lbm_residual(h, stream, &r, nullptr, nullptr)) != LBM_OK) return rc;
+        if (history && checks < history_len) history[checks] = r;
+        ++checks;
+        if (r < tol_max_dT) break;
+    }
+    if (steps_taken) *steps_taken = done;
+    if (final_max_dT) *final_max_dT = r;
+    return LBM_OK;
+}
+
+int lbm_centerline_peaks(lbm_t *h, void *stream, double out[5]) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = lbmk::launch_centerline(h, s);
+    if (e != hipSuccess) return hip_fail(h, e, "centreline kernel");
+    double pk[4];
+    if ((rc = read_res(h, s, lbmk::kResPeak, 4, pk)) != LBM_OK) return rc;
+    double raw[LBM_NRAW];
+    if ((rc = lbm_observables_raw(h, stream, raw)) != LBM_OK) return rc;
+    const double N = h->p.N, U = h->p.U;
+    out[0] = pk[0] / U;
+    out[1] = (pk[1] + 0.5) / N;
+    out[2] = pk[2] / U;
+    out[3] = (pk[3] + 0.5) / N;
+    out[4] = 0.5 * raw[LBM_RAW_U2] / (U * U);
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(out[k])) return fail(h, LBM_EDIVERGED, "non-finite centreline value");
+    return LBM_OK;
+}
+
 int lbm_profile(lbm_t *h, int enable) {
     if (!h) return LBM_EINVAL;
     h->profiling = enable != 0;

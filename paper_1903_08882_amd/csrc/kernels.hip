@@ -702,6 +702,52 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_obs(const double *__rest
     if (threadIdx.x == 0 && accumulate) res[kResAcc + LBM_NRAW] += 1.0;
 }
 
+// Maximum of u on the line x = y = 1/2 (over z) and of w on y = z = 1/2 (over
+// x), one block per line; for even N the two central nodes are averaged.
+// Ties go to the smaller index.  res[kResPeak + 0..3] = u_max, k_u, w_max, k_w.
+__global__ __launch_bounds__(kRedBlock) void k_centerline(int N, const double *__restrict__ macro,
+                                                          double *__restrict__ res) {
+    const uint64_t V = static_cast<uint64_t>(N) * N * N, N2 = static_cast<uint64_t>(N) * N;
+    const int lo = (N - 1) / 2, hi = N / 2;
+    const bool horiz = blockIdx.x == 1;             // 0: u along z, 1: w along x
+    const double *phi = macro + (horiz ? 3 : 1) * V;
+    double best = -INFINITY;
+    int arg = 0;
+    for (int k = threadIdx.x; k < N; k += kRedBlock) {
+        double v;
+        if (!horiz)  // x = y = centre, varying z
+            v = 0.25 * (phi[lo + N * lo + N2 * k] + phi[hi + N * lo + N2 * k] +
+                        phi[lo + N * hi + N2 * k] + phi[hi + N * hi + N2 * k]);
+        else         // y = z = centre, varying x
+            v = 0.25 * (phi[k + N * lo + N2 * lo] + phi[k + N * hi + N2 * lo] +
+                        phi[k + N * lo + N2 * hi] + phi[k + N * hi + N2 * hi]);
+        if (v > best) {
+            best = v;
+            arg = k;
+        }
+    }
+    __shared__ double sv[kRedBlock];
+    __shared__ int si[kRedBlock];
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = arg;
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double a = sv[threadIdx.x], b = sv[threadIdx.x + w];
+            const int ia = si[threadIdx.x], ib = si[threadIdx.x + w];
+            if (b > a || (b == a && ib < ia)) {
+                sv[threadIdx.x] = b;
+                si[threadIdx.x] = ib;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        res[kResPeak + 2 * blockIdx.x] = sv[0];
+        res[kResPeak + 2 * blockIdx.x + 1] = si[0];
+    }
+}
+
 __global__ void k_reset_acc(double *__restrict__ res) {
     if (threadIdx.x <= LBM_NRAW) res[kResAcc + threadIdx.x] = 0.0;
 }
@@ -929,6 +975,14 @@ hipError_t launch_residual(const lbm_t *h, hipStream_t s) {
     k_fold_rows<5, true><<<kFold, kRedBlock, 0, s>>>(part, h->L.nblk_red, per, fold);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_finalize_residual<<<1, kRedBlock, 0, s>>>(fold, kFold, dptr(h, h->L.off_res));
+    return hipGetLastError();
+}
+
+hipError_t launch_centerline(const lbm_t *h, hipStream_t s) {
+    double *macro = dptr(h, h->L.off_macro);
+    hipError_t e = launch_macro(h, macro, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_centerline<<<2, kRedBlock, 0, s>>>(h->geo.N, macro, dptr(h, h->L.off_res));
     return hipGetLastError();
 }
 

@@ -97,11 +97,14 @@ hipError_t launch_reset_acc(const lbm_t *h, hipStream_t s);
 // Residual against the snapshot into res[64..66], then snapshot := current.
 hipError_t launch_residual(const lbm_t *h, hipStream_t s);
 hipError_t launch_snapshot(const lbm_t *h, hipStream_t s);
+// Centreline maxima of u (over z) and w (over x) into res[kResPeak..+3].
+hipError_t launch_centerline(const lbm_t *h, hipStream_t s);
 
 // Offsets (in doubles) of the result block.
 constexpr int kResCur = 0;
 constexpr int kResAcc = 32;   // LBM_NRAW sums, then the sample count
 constexpr int kResResid = 64;
+constexpr int kResPeak = 72;
 constexpr int kResDoubles = 96;
 
 }  // namespace lbmk

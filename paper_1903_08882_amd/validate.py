@@ -1,0 +1,88 @@
+"""Side-heated cavity to steady state on the GPU, compared with the paper's
+benchmark values (Sec. 3, Tables 1 and 2).
+
+    python -m paper_1903_08882_amd.validate --N 129 --Ra 1e6
+
+Runs the C-ABI steady-state driver (max |dT| over `--check` steps below
+`--tol`) from rest with seeded noise, then reports the hot- and cold-wall
+Nusselt numbers (overall and mid-plane line; link flux and one-sided
+difference), the mid-plane centreline velocity maxima with their positions,
+the kinetic energy E, and the paper's values for the same grid and Ra.  The
+paper's hot and cold walls are y = 0 and y = 1; here they are x = 0 and x = 1,
+so its v_max (location z) is our u_max (location z) and its w_max (location y)
+is our w_max (location x).
+"""
+import argparse
+import json
+import time
+
+import torch
+
+from . import binding as B
+from . import synth
+
+# Sec. 3, Table 1 (v_max, z, w_max, y, E x 1e3) and Table 2 (Nu_mean and
+# Nu_overall at the hot wall y = 0 and the cold wall y = 1), "Present" rows.
+PAPER = {
+    (81, 1e6): dict(v_max=0.08056, z=0.8580, w_max=0.25437, y=0.0432, E=3.3346e-3,
+                    Nu_mean_hot=8.99850, Nu_mean_cold=8.99333, Nu_hot=8.75450, Nu_cold=8.75405),
+    (129, 1e6): dict(v_max=0.08091, z=0.8566, w_max=0.25753, y=0.0349, E=3.3280e-3,
+                     Nu_mean_hot=8.91688, Nu_mean_cold=8.91467, Nu_hot=8.67775, Nu_cold=8.67746),
+    (161, 1e6): dict(v_max=0.08099, z=0.8540, w_max=0.25729, y=0.0404, E=3.3265e-3,
+                     Nu_mean_hot=8.89886, Nu_mean_cold=8.89744, Nu_hot=8.66075, Nu_cold=8.66060),
+    (257, 1e6): dict(v_max=0.08107, z=0.8541, w_max=0.25836, y=0.0370, E=3.3248e-3,
+                     Nu_mean_hot=8.88054, Nu_mean_cold=8.87994, Nu_hot=8.64345, Nu_cold=8.64342),
+    (81, 1e7): dict(v_max=0.05410, z=0.8951, w_max=0.25865, y=0.0185, E=1.8418e-3,
+                    Nu_mean_hot=17.26877, Nu_mean_cold=17.31377, Nu_hot=17.03864, Nu_cold=17.09483),
+    (129, 1e7): dict(v_max=0.05671, z=0.8798, w_max=0.26054, y=0.0194, E=1.8365e-3,
+                     Nu_mean_hot=16.85522, Nu_mean_cold=16.85465, Nu_hot=16.64342, Nu_cold=16.64642),
+    (161, 1e7): dict(v_max=0.05730, z=0.8789, w_max=0.26184, y=0.0217, E=1.8345e-3,
+                     Nu_mean_hot=16.73787, Nu_mean_cold=16.73588, Nu_hot=16.52963, Nu_cold=16.52950),
+    (257, 1e7): dict(v_max=0.05789, z=0.8774, w_max=0.26181, y=0.0214, E=1.8322e-3,
+                     Nu_mean_hot=16.60871, Nu_mean_cold=16.60782, Nu_hot=16.40322, Nu_cold=16.40285),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--N", type=int, default=129)
+    ap.add_argument("--Ra", type=float, default=1e6)
+    ap.add_argument("--Pr", type=float, default=0.71)
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--check", type=int, default=1000)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-steps", type=int, default=2_000_000)
+    a = ap.parse_args()
+
+    h = B.lbm_create(a.N, a.Ra, a.Pr, "side_heated", a.storage)
+    B.lbm_set_fields(h, torch.from_numpy(synth.rest_with_noise(a.N).reshape(-1)).cuda())
+    t0 = time.perf_counter()
+    steps, r, hist = 0, float("inf"), []
+    chunk = 100 * a.check                      # report progress every 100 checks
+    while steps < a.max_steps and not r < a.tol:
+        k, r, hh = B.lbm_run_to_steady(h, a.check, a.tol, min(chunk, a.max_steps - steps),
+                                       history_len=100)
+        steps += k
+        hist += hh
+        print(f"# step {steps}  max_dT {r:.3e}  {time.perf_counter() - t0:.1f} s", flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nd = B.lbm_nondimensional(B.lbm_get_params(h), B.lbm_observables_raw(h))
+    pk = B.lbm_centerline_peaks(h)
+    out = {"N": a.N, "Ra": a.Ra, "Pr": a.Pr, "storage": a.storage, "steps": steps,
+           "max_dT": r, "converged": r < a.tol, "wall_s": round(wall, 2),
+           "MLUPS": round(a.N ** 3 * steps / wall / 1e6, 1),
+           "Nu_hot": nd["Nu_hot"], "Nu_cold": nd["Nu_cold"], "Nu_mean_hot": nd["Nu_hot_mid"],
+           "Nu_mean_cold": nd["Nu_cold_mid"], "Nu_hot_fd": nd["Nu_hot_fd"],
+           "Nu_cold_fd": nd["Nu_cold_fd"], "Nu_mean_hot_fd": nd["Nu_hot_mid_fd"],
+           "v_max": pk["u_max"], "z": pk["u_max_z"], "w_max": pk["w_max"], "y": pk["w_max_x"],
+           "E": pk["E"], "residual_every_10_checks": hist[::10]}
+    ref = PAPER.get((a.N, a.Ra))
+    if ref and abs(a.Pr - 0.71) < 1e-12:
+        out["paper"] = ref
+        out["rel_diff"] = {k: (out[k] - v) / v for k, v in ref.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

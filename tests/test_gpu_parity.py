@@ -333,3 +333,50 @@ def test_full_size_257_one_step_against_oracle():
     del before
     o.step(1)
     assert_pop_close(after, o.pop, o.p, 1e-5, "257^3 one step")
+
+
+# --------------------------------------------------------------------------
+# Drivers and diagnostics
+# --------------------------------------------------------------------------
+
+def test_run_to_steady_reaches_conduction_below_onset():
+    """Rayleigh-Benard at Ra = 1e3 (far below onset): the native driver stops
+    once max |dT| over 1000 steps is below 1e-10; T then matches the oracle
+    after the same number of steps and is the linear conduction profile."""
+    N = 10
+    h = B.lbm_create(N, 1e3, 0.71, 1, "fp64")
+    B.lbm_set_fields(h, dev(synth.rest_with_noise(N)))
+    steps, r, hist = B.lbm_run_to_steady(h, 1000, 1e-10, 60000, history_len=60)
+    say(f"steady after {steps} steps, max dT {r:.3g}")
+    assert r < 1e-10 and steps < 60000
+    assert len(hist) == steps // 1000 and hist[-1] == r
+    o = oracle.Oracle(N, 1e3, 0.71, 1)
+    o.init_fields(synth.rest_with_noise(N))
+    o.step(steps)
+    mg = B.lbm_get_fields(h).cpu().numpy().reshape(5, -1)
+    assert np.abs(mg[4] - o.macro()[4]).max() < 1e-12
+    # the undamped (-1)^(z+t) checkerboard of the closed cell (see the oracle's
+    # below-onset test) leaves T = linear + O(1e-7): compare the two-step mean
+    B.lbm_step(h, 1)
+    m2 = B.lbm_get_fields(h).cpu().numpy().reshape(5, -1)
+    z = (np.arange(N) + 0.5) / N
+    T = 0.5 * (mg[4] + m2[4]).reshape(N, N, N)
+    assert np.abs(T - (0.5 - z)[:, None, None]).max() < 1e-9
+
+
+@pytest.mark.parametrize("N", [15, 16])
+def test_centerline_peaks_against_oracle_fields(N):
+    pr = Pair(N, 1e5, 0.71, 0, "fp64", U=0.1)
+    pr.init_rich()
+    pr.step(23)
+    got = B.lbm_centerline_peaks(pr.h)
+    m = pr.o.macro().reshape(5, N, N, N)        # [q][z][y][x]
+    lo, hi = (N - 1) // 2, N // 2
+    u_line = 0.25 * (m[1][:, lo, lo] + m[1][:, lo, hi] + m[1][:, hi, lo] + m[1][:, hi, hi])
+    w_line = 0.25 * (m[3][lo, lo, :] + m[3][lo, hi, :] + m[3][hi, lo, :] + m[3][hi, hi, :])
+    U = pr.p.U
+    assert abs(got["u_max"] - u_line.max() / U) < 1e-12
+    assert abs(got["u_max_z"] - (np.argmax(u_line) + 0.5) / N) < 1e-15
+    assert abs(got["w_max"] - w_line.max() / U) < 1e-12
+    assert abs(got["w_max_x"] - (np.argmax(w_line) + 0.5) / N) < 1e-15
+    assert abs(got["E"] - 0.5 * (m[1:4] ** 2).sum(0).mean() / U ** 2) < 1e-12
