@@ -25,9 +25,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 METRIC = "coupled-lattice MLUPS & % HBM roofline; steps-to-steady vs plain at Nu ±0.5%"
-# bytes of one node's 26 populations in HBM (FP16 storage keeps the resting
-# thermal population g_0 in FP32); a step reads and writes each once
-NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 25 * 2 + 4}
+# bytes of one node's 26 populations in HBM (FP16 storage keeps the seven
+# thermal populations in FP32); a step reads and writes each once
+NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 19 * 2 + 7 * 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage / f32 compute"}
 
 

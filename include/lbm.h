@@ -54,14 +54,16 @@ extern "C" {
 #define LBM_API __attribute__((visibility("default")))
 #endif
 
-typedef struct lbm lbm_t; /* opaque handle; owned by the library */
+typedef struct lbm lbm_t;             /* opaque handle; owned by the library */
+typedef struct lbm_batch lbm_batch_t; /* opaque batch of cavities           */
 
 enum lbm_cell { LBM_SIDE_HEATED = 0, LBM_RAYLEIGH_BENARD = 1 };
 
 /* Storage type of the populations in device memory.  Populations are kept as
  * deviations from the rest equilibrium (f_i - w_i, g_i - w_i^T * 0).
  * FP64: FP64 storage and arithmetic.  FP32: FP32 storage and arithmetic.
- * FP16S: FP16 storage of the scaled deviations, FP32 arithmetic. */
+ * FP16S: f as FP16 scaled deviations, g as FP32; FP32 arithmetic
+ * (66 bytes per node instead of 104). */
 enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 };
 
 enum lbm_status {
@@ -237,6 +239,57 @@ LBM_API int lbm_run_to_steady(lbm_t *h, int64_t check_every, double tol_max_dT,
  * <|u|^2>/(2 U^2).  Nodal values at (i + 1/2)/N; for even N the two central
  * lines are averaged.  Synchronises stream. */
 LBM_API int lbm_centerline_peaks(lbm_t *h, void *stream, double out[5]);
+
+/* Fields (u, v, w, T) trilinearly resampled onto M^3 node-centred points
+ * (i + 1/2)/M, FP32 [4][M^3] in device memory.  Per axis the samples are the
+ * nodes and, beyond the outermost nodes, the walls: u = v = w = 0 on all
+ * walls, T = T_w on the isothermal walls, T held at the nearest node along
+ * the adiabatic axes.  M >= 2. */
+LBM_API int lbm_resample_fields(lbm_t *h, int M, float *out, void *stream);
+
+/* Block-size autotuner: times the step kernel with 64, 128, 192 and 256
+ * threads per block (steps_per_candidate steps each, HIP events on stream)
+ * and keeps the fastest for this handle.  Results are cached per (N,
+ * storage, cell) for the life of the process; a cached entry is reused
+ * without timing.  The steps taken while timing advance the state like
+ * lbm_step.  *best_ms is the mean step time of the winner (0 if cached). */
+LBM_API int lbm_autotune(lbm_t *h, void *stream, int steps_per_candidate, int *best_block,
+                         double *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Batches: K independent cavities (own N, Ra, Pr, cell; one storage type)
+ * advanced together, one kernel launch per step for all of them, so that
+ * small lattices are not launch bound.  Each cavity is an ordinary handle
+ * (lbm_batch_cavity) whose memory is a slice of the batch buffer: use it to
+ * set and read fields, observables and residuals.  A cavity handle of a batch
+ * cannot be stepped on its own (LBM_ESTATE); set its fields only while the
+ * batch has taken an even number of steps.
+ * ------------------------------------------------------------------------- */
+LBM_API int lbm_batch_state_bytes(int K, const int *N, int storage, size_t *bytes);
+LBM_API int lbm_batch_create(int K, const int *N, const double *Ra, const double *Pr,
+                             const int *cell, int storage, const lbm_opts *opts, void *dev_buf,
+                             size_t buf_bytes, lbm_batch_t **out);
+LBM_API int lbm_batch_destroy(lbm_batch_t *b);
+LBM_API int lbm_batch_cavity(lbm_batch_t *b, int k, lbm_t **h);
+
+/* Advance every active cavity by n steps (asynchronous on stream). */
+LBM_API int lbm_batch_step(lbm_batch_t *b, int64_t n, void *stream);
+
+/* Steady-state loop over the batch: every check_every steps each active
+ * cavity's max |dT| is taken (as lbm_residual); cavities below tol_max_dT
+ * retire (are no longer stepped).  Stops when all have retired or after
+ * max_steps.  A cavity whose residual is not finite (diverged) retires too,
+ * with res_k = NaN, and the others go on.  steps_k[k] = steps cavity k took,
+ * res_k[k] = its last max |dT| (either may be NULL). */
+LBM_API int lbm_batch_run_to_steady(lbm_batch_t *b, int64_t check_every, double tol_max_dT,
+                                    int64_t max_steps, void *stream, int64_t *steps_k,
+                                    double *res_k);
+
+/* Autotuner for the batched launch (as lbm_autotune, not cached). */
+LBM_API int lbm_batch_autotune(lbm_batch_t *b, void *stream, int steps_per_candidate,
+                               int *best_block, double *best_ms);
+
+LBM_API const char *lbm_batch_last_error(const lbm_batch_t *b);
 
 /* Kernel timing.  With profiling enabled, lbm_step brackets every step
  * kernel it launches with a pair of HIP events on its stream.

@@ -86,6 +86,21 @@ _SIG = {
     "lbm_run_to_steady": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, _P,
                                          ctypes.POINTER(ctypes.c_int64), _D, _D, ctypes.c_int64]),
     "lbm_centerline_peaks": (ctypes.c_int, [_P, _P, _D]),
+    "lbm_resample_fields": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "lbm_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
+    "lbm_batch_state_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                        ctypes.POINTER(lbm_opts), _P, ctypes.c_size_t,
+                                        ctypes.POINTER(_P)]),
+    "lbm_batch_destroy": (ctypes.c_int, [_P]),
+    "lbm_batch_cavity": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_P)]),
+    "lbm_batch_step": (ctypes.c_int, [_P, ctypes.c_int64, _P]),
+    "lbm_batch_run_to_steady": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, _P,
+                                               ctypes.POINTER(ctypes.c_int64), _D]),
+    "lbm_batch_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
+    "lbm_batch_last_error": (ctypes.c_char_p, [_P]),
     "lbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "lbm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
@@ -169,7 +184,7 @@ class Handle:
         self.V = N ** 3
 
     def __del__(self):
-        if getattr(self, "ptr", None) and _lib is not None:
+        if getattr(self, "ptr", None) and _lib is not None and not getattr(self, "owned_by_batch", False):
             _lib.lbm_destroy(self.ptr)
             self.ptr = None
 
@@ -283,6 +298,114 @@ def lbm_centerline_peaks(h, stream=None):
     out = (ctypes.c_double * 5)()
     _check(lib().lbm_centerline_peaks(h.ptr, _stream(stream), out), h.ptr)
     return dict(zip(["u_max", "u_max_z", "w_max", "w_max_x", "E"], list(out)))
+
+
+def lbm_resample_fields(h, M, out=None, stream=None):
+    """(u, v, w, T) on M^3 node-centred points: CUDA float32 tensor [4][M^3]."""
+    out = out if out is not None else torch.empty(4 * M ** 3, dtype=torch.float32, device=h.buf.device)
+    _check(lib().lbm_resample_fields(h.ptr, int(M), _dev_ptr(out, torch.float32, 4 * M ** 3),
+                                     _stream(stream)), h.ptr)
+    return out
+
+
+def lbm_autotune(h, steps_per_candidate=20, stream=None):
+    """(best block size, its mean step time in ms; 0 when taken from the cache)."""
+    blk = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().lbm_autotune(h.ptr, _stream(stream), int(steps_per_candidate), ctypes.byref(blk),
+                              ctypes.byref(ms)), h.ptr)
+    return blk.value, ms.value
+
+
+class Batch:
+    """An lbm_batch_t* with its torch buffer and per-cavity handles."""
+
+    def __init__(self, ptr, buf, Ns):
+        self.ptr = ptr
+        self.buf = buf
+        self.Ns = list(Ns)
+        self.cavities = []
+        for k, N in enumerate(self.Ns):
+            hp = ctypes.c_void_p()
+            _bcheck(lib().lbm_batch_cavity(ptr, k, ctypes.byref(hp)), ptr)
+            c = Handle(hp, buf, N)
+            c.owned_by_batch = True
+            self.cavities.append(c)
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            for c in self.cavities:
+                c.ptr = None           # destroyed with the batch
+            _lib.lbm_batch_destroy(self.ptr)
+            self.ptr = None
+
+
+def _bcheck(rc, b=None):
+    if rc != 0:
+        msg = lib().lbm_batch_last_error(b).decode() if b else lib().lbm_strerror(rc).decode()
+        raise LBMError(rc, msg or lib().lbm_strerror(rc).decode())
+
+
+def _ints(v):
+    return (ctypes.c_int * len(v))(*[int(x) for x in v])
+
+
+def _dbls(v):
+    return (ctypes.c_double * len(v))(*[float(x) for x in v])
+
+
+def lbm_batch_state_bytes(Ns, storage="fp32"):
+    b = ctypes.c_size_t()
+    _check(lib().lbm_batch_state_bytes(len(Ns), _ints(Ns), STORAGES.get(storage, storage),
+                                       ctypes.byref(b)))
+    return b.value
+
+
+def lbm_batch_create(Ns, Ras, Prs, cells, storage="fp32", opts=None, device=None):
+    nbytes = lbm_batch_state_bytes(Ns, storage)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+    o = opts if opts is not None else lbm_default_opts()
+    b = ctypes.c_void_p()
+    cells = [CELLS.get(c, c) for c in cells]
+    _check(lib().lbm_batch_create(len(Ns), _ints(Ns), _dbls(Ras), _dbls(Prs), _ints(cells),
+                                  STORAGES.get(storage, storage), ctypes.byref(o),
+                                  ctypes.c_void_p(buf.data_ptr()), nbytes, ctypes.byref(b)))
+    return Batch(b, buf, Ns)
+
+
+def lbm_batch_cavity(b, k):
+    """The handle of cavity k (owned by the batch)."""
+    return b.cavities[k]
+
+
+def lbm_batch_destroy(b):
+    if b.ptr:
+        for c in b.cavities:
+            c.ptr = None
+        _bcheck(lib().lbm_batch_destroy(b.ptr))
+        b.ptr = None
+
+
+def lbm_batch_step(b, n=1, stream=None):
+    _bcheck(lib().lbm_batch_step(b.ptr, int(n), _stream(stream)), b.ptr)
+
+
+def lbm_batch_run_to_steady(b, check_every=1000, tol_max_dT=1e-8, max_steps=10**6, stream=None):
+    """(steps each cavity took, last max |dT| of each cavity)."""
+    K = len(b.Ns)
+    steps = (ctypes.c_int64 * K)()
+    res = (ctypes.c_double * K)()
+    _bcheck(lib().lbm_batch_run_to_steady(b.ptr, int(check_every), float(tol_max_dT), int(max_steps),
+                                          _stream(stream), steps, res), b.ptr)
+    return list(steps), list(res)
+
+
+def lbm_batch_autotune(b, steps_per_candidate=20, stream=None):
+    blk = ctypes.c_int()
+    ms = ctypes.c_double()
+    _bcheck(lib().lbm_batch_autotune(b.ptr, _stream(stream), int(steps_per_candidate),
+                                     ctypes.byref(blk), ctypes.byref(ms)), b.ptr)
+    return blk.value, ms.value
 
 
 def lbm_profile(h, enable=True):

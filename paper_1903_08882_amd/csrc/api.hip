@@ -4,7 +4,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 #include "lbm_internal.h"
 
@@ -215,6 +218,7 @@ int lbm_get_populations(lbm_t *h, double *out, void *stream) {
 int lbm_step(lbm_t *h, int64_t n, void *stream) {
     int rc = require_init(h);
     if (rc) return rc;
+    if (h->in_batch) return fail(h, LBM_ESTATE, "cavity of a batch: step it with lbm_batch_step");
     if (n < 0) return fail(h, LBM_EINVAL, "negative step count");
     hipStream_t s = as_stream(stream);
     for (int64_t k = 0; k < n; ++k) {
@@ -409,6 +413,302 @@ int lbm_profile_read(lbm_t *h, double *kernel_ms, int64_t *kernels) {
     h->events_used = 0;
     return LBM_OK;
 }
+
+int lbm_resample_fields(lbm_t *h, int M, float *out, void *stream) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!out || M < 2 || M > lbmk::kMaxN) return fail(h, LBM_EINVAL, "bad output size or pointer");
+    hipError_t e = lbmk::launch_resample(h, M, out, as_stream(stream));
+    return e == hipSuccess ? LBM_OK : hip_fail(h, e, "resample");
+}
+
+}  // extern "C"
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune_cache;   // (N, storage, cell) -> block
+
+// Mean duration (ms) of `steps` launches of fn on stream s, timed with events.
+template <class F>
+int time_steps(F &&fn, int steps, hipStream_t s, double *ms_out, std::string *err) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return LBM_EDEVICE;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return LBM_EDEVICE;
+    }
+    int rc = fn(2);   // warm-up
+    if (rc == LBM_OK && hipEventRecord(a, s) != hipSuccess) rc = LBM_EDEVICE;
+    if (rc == LBM_OK) rc = fn(steps);
+    if (rc == LBM_OK && hipEventRecord(b, s) != hipSuccess) rc = LBM_EDEVICE;
+    float ms = 0.0f;
+    if (rc == LBM_OK && (hipEventSynchronize(b) != hipSuccess ||
+                         hipEventElapsedTime(&ms, a, b) != hipSuccess)) {
+        rc = LBM_EDEVICE;
+        *err = "timing events failed";
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms_out = ms / steps;
+    return rc;
+}
+
+constexpr int kTuneCandidates[] = {64, 128, 192, 256};
+
+}  // namespace
+
+extern "C" {
+
+int lbm_autotune(lbm_t *h, void *stream, int steps_per_candidate, int *best_block, double *best_ms) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (steps_per_candidate < 1) return fail(h, LBM_EINVAL, "steps_per_candidate < 1");
+    const auto key = std::make_tuple(h->p.N, h->storage, h->p.cell);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            h->block = it->second;
+            if (best_block) *best_block = h->block;
+            if (best_ms) *best_ms = 0.0;
+            return LBM_OK;
+        }
+    }
+    hipStream_t s = as_stream(stream);
+    int best = h->block;
+    double best_t = INFINITY;
+    for (int cand : kTuneCandidates) {
+        h->block = cand;
+        double ms = 0.0;
+        rc = time_steps([&](int n) { return lbm_step(h, n, stream); }, steps_per_candidate, s, &ms, &h->err);
+        if (rc != LBM_OK) return rc;
+        if (ms < best_t) {
+            best_t = ms;
+            best = cand;
+        }
+    }
+    h->block = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    if (best_block) *best_block = best;
+    if (best_ms) *best_ms = best_t;
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+int bfail(lbm_batch_t *b, int code, const std::string &msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t table_bytes(int K) { return up256(static_cast<size_t>(K) * lbmk::kMaxDescBytes); }
+
+// Write the descriptor table (geometry, coefficients, active flags) to the device.
+int upload_table(lbm_batch_t *b) {
+    std::vector<char> img(table_bytes(b->K));
+    size_t nbytes = 0;
+    hipError_t e = lbmk::build_batch_table(b, img.data(), &nbytes);
+    if (e == hipSuccess)
+        e = hipMemcpy(static_cast<char *>(b->buf) + b->off_table, img.data(), nbytes,
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("descriptor table: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_state_bytes(int K, const int *N, int storage, size_t *bytes) {
+    if (K < 1 || !N || !bytes) return LBM_EINVAL;
+    size_t total = table_bytes(K);
+    for (int k = 0; k < K; ++k) {
+        size_t s = 0;
+        int rc = lbm_state_bytes(N[k], storage, &s);
+        if (rc != LBM_OK) return rc;
+        total += up256(s);
+    }
+    *bytes = total;
+    return LBM_OK;
+}
+
+int lbm_batch_create(int K, const int *N, const double *Ra, const double *Pr, const int *cell,
+                     int storage, const lbm_opts *opts, void *dev_buf, size_t buf_bytes,
+                     lbm_batch_t **out) {
+    if (!out || K < 1 || !N || !Ra || !Pr || !cell) return LBM_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    int rc = lbm_batch_state_bytes(K, N, storage, &need);
+    if (rc != LBM_OK) return rc;
+    if (dev_buf && (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return LBM_EINVAL;
+    if (dev_buf && buf_bytes < need) return LBM_ENOMEM;
+    lbm_opts o;
+    lbm_default_opts(&o);
+    if (opts) o = *opts;
+    o.sample_every = 0;   // batches do not sample time averages
+    lbm_batch_t *b = new (std::nothrow) lbm_batch;
+    if (!b) return LBM_ENOMEM;
+    b->K = K;
+    b->storage = storage;
+    b->block = o.block ? o.block : 256;
+    if (dev_buf) {
+        b->buf = dev_buf;
+    } else {
+        if (hipMalloc(&b->buf, need) != hipSuccess) {
+            delete b;
+            return LBM_ENOMEM;
+        }
+        b->own_buf = true;
+    }
+    b->off_table = 0;
+    size_t off = table_bytes(K);
+    for (int k = 0; k < K; ++k) {
+        size_t s = 0;
+        lbm_state_bytes(N[k], storage, &s);
+        lbm_t *h = nullptr;
+        rc = lbm_create(N[k], Ra[k], Pr[k], cell[k], storage, &o, static_cast<char *>(b->buf) + off,
+                        s, &h);
+        if (rc != LBM_OK) {
+            lbm_batch_destroy(b);
+            return rc;
+        }
+        h->in_batch = true;
+        h->block = b->block;
+        b->cav.push_back(h);
+        b->active.push_back(1);
+        b->last_res.push_back(INFINITY);
+        off += up256(s);
+    }
+    if ((rc = upload_table(b)) != LBM_OK) {
+        lbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch_t *b) {
+    if (!b) return LBM_EINVAL;
+    for (lbm_t *h : b->cav) lbm_destroy(h);
+    if (b->own_buf) (void)hipFree(b->buf);
+    delete b;
+    return LBM_OK;
+}
+
+int lbm_batch_cavity(lbm_batch_t *b, int k, lbm_t **h) {
+    if (!b || !h || k < 0 || k >= b->K) return LBM_EINVAL;
+    *h = b->cav[k];
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch_t *b, int64_t n, void *stream) {
+    if (!b) return LBM_EINVAL;
+    if (n < 0) return bfail(b, LBM_EINVAL, "negative step count");
+    for (int k = 0; k < b->K; ++k) {
+        const lbm_t *h = b->cav[k];
+        if (!b->active[k]) continue;
+        if (!h->initialised) return bfail(b, LBM_ESTATE, "cavity " + std::to_string(k) + " has no populations");
+        if (h->parity != b->parity)
+            return bfail(b, LBM_ESTATE, "cavity " + std::to_string(k) + " was set after an odd number of batch steps");
+    }
+    hipStream_t s = as_stream(stream);
+    for (int64_t i = 0; i < n; ++i) {
+        hipError_t e = lbmk::launch_step_batch(b, b->parity, s);
+        if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batched step: ") + hipGetErrorString(e));
+        b->parity ^= 1;
+        b->t += 1;
+        for (int k = 0; k < b->K; ++k)
+            if (b->active[k]) {
+                lbm_t *h = b->cav[k];
+                h->parity ^= 1;
+                h->t += 1;
+                h->has_flux = true;
+            }
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_run_to_steady(lbm_batch_t *b, int64_t check_every, double tol_max_dT,
+                            int64_t max_steps, void *stream, int64_t *steps_k, double *res_k) {
+    if (!b) return LBM_EINVAL;
+    if (check_every <= 0 || max_steps < 0 || !(tol_max_dT >= 0.0))
+        return bfail(b, LBM_EINVAL, "bad check interval, step limit or tolerance");
+    int64_t done = 0;
+    int rc = LBM_OK;
+    auto any_active = [&] {
+        for (int a : b->active)
+            if (a) return true;
+        return false;
+    };
+    while (done < max_steps && any_active()) {
+        const int64_t k = check_every < max_steps - done ? check_every : max_steps - done;
+        if ((rc = lbm_batch_step(b, k, stream)) != LBM_OK) return rc;
+        done += k;
+        bool changed = false;
+        for (int c = 0; c < b->K; ++c) {
+            if (!b->active[c]) continue;
+            double r = 0.0;
+            rc = lbm_residual(b->cav[c], stream, &r, nullptr, nullptr);
+            if (rc == LBM_EDIVERGED) {   // quarantine: retire it, keep the others going
+                r = NAN;
+            } else if (rc != LBM_OK) {
+                return bfail(b, rc, "cavity " + std::to_string(c) + ": " + b->cav[c]->err);
+            }
+            b->last_res[c] = r;
+            if (!(r >= tol_max_dT)) {    // converged, or diverged (NaN)
+                b->active[c] = 0;
+                changed = true;
+            }
+        }
+        if (changed && (rc = upload_table(b)) != LBM_OK) return rc;
+    }
+    for (int c = 0; c < b->K; ++c) {
+        if (steps_k) steps_k[c] = b->cav[c]->t;
+        if (res_k) res_k[c] = b->last_res[c];
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch_t *b, void *stream, int steps_per_candidate, int *best_block,
+                       double *best_ms) {
+    if (!b) return LBM_EINVAL;
+    if (steps_per_candidate < 1) return bfail(b, LBM_EINVAL, "steps_per_candidate < 1");
+    hipStream_t s = as_stream(stream);
+    int best = b->block;
+    double best_t = INFINITY;
+    for (int cand : kTuneCandidates) {
+        b->block = cand;
+        int rc = upload_table(b);
+        if (rc != LBM_OK) return rc;
+        double ms = 0.0;
+        rc = time_steps([&](int n) { return lbm_batch_step(b, n, stream); }, steps_per_candidate, s, &ms, &b->err);
+        if (rc != LBM_OK) return rc;
+        if (ms < best_t) {
+            best_t = ms;
+            best = cand;
+        }
+    }
+    b->block = best;
+    for (lbm_t *h : b->cav) h->block = best;
+    int rc = upload_table(b);
+    if (rc != LBM_OK) return rc;
+    if (best_block) *best_block = best;
+    if (best_ms) *best_ms = best_t;
+    return LBM_OK;
+}
+
+const char *lbm_batch_last_error(const lbm_batch_t *b) { return b ? b->err.c_str() : "NULL batch"; }
 
 const char *lbm_last_error(const lbm_t *h) { return h ? h->err.c_str() : "NULL handle"; }
 

@@ -15,9 +15,8 @@
 // near copy bandwidth on HBM.)
 // f is stored as the deviation f_i - w_i from the rest equilibrium (rho = 1,
 // u = 0), g as is (its rest equilibrium at the mean wall temperature 0 is
-// zero).  FP16 storage scales the moving populations by a power of two and
-// keeps the resting thermal population g_0 (about w_0^T T, up to 0.47) in
-// FP32: resting populations never move, so their width is free to choose.
+// zero).  FP16 storage keeps f as FP16 (scaled by a power of two) and g in
+// FP32; slots of one sub-block may have different widths.
 //
 // Streaming uses the in-place AA pattern, so each step reads and writes the
 // same 26 slots per node and the state needs one copy:
@@ -62,22 +61,31 @@ __host__ __device__ constexpr double wrest(int i) {
 // ---------------------------------------------------------------------------
 // Storage codecs
 // ---------------------------------------------------------------------------
-// S: storage type of a moving population, W: of the resting thermal
-// population g_0, R: arithmetic type.
-struct CF64 { using S = double; using W = double; using R = double; };
-struct CF32 { using S = float; using W = float; using R = float; };
-struct CF16 { using S = _Float16; using W = float; using R = float; };
+// S: storage type of the narrow populations, W: of the wide ones (the first
+// GW thermal populations g_0 .. g_{GW-1}), R: arithmetic type.  FP16 storage
+// keeps all seven thermal populations in FP32: with only g_0 wide the
+// temperature carries FP16 noise of ~1e-4 and the 129^3, Ra 1e6 steady Nu is
+// 0.85% low; with all of g wide it is within 0.12% (f stays FP16).
+struct CF64 { using S = double; using W = double; using R = double; static constexpr int GW = 1; };
+struct CF32 { using S = float; using W = float; using R = float; static constexpr int GW = 1; };
+struct CF16 { using S = _Float16; using W = float; using R = float; static constexpr int GW = kQG; };
 
 // Storage width and byte start (per node of a sub-block) of population q.
 template <class C>
+__host__ __device__ constexpr bool wide(int q) {
+    return q >= kQF && q < kQF + C::GW;
+}
+template <class C>
 __host__ __device__ constexpr uint32_t qsize(int q) {
-    return q == kQF ? sizeof(typename C::W) : sizeof(typename C::S);
+    return wide<C>(q) ? sizeof(typename C::W) : sizeof(typename C::S);
 }
 template <class C>
 __host__ __device__ constexpr uint32_t qstart(int q) {
     return q <= kQF ? q * sizeof(typename C::S)
-                    : kQF * sizeof(typename C::S) + sizeof(typename C::W) +
-                          (q - kQF - 1) * sizeof(typename C::S);
+                    : (q <= kQF + C::GW
+                           ? kQF * sizeof(typename C::S) + (q - kQF) * sizeof(typename C::W)
+                           : kQF * sizeof(typename C::S) + C::GW * sizeof(typename C::W) +
+                                 (q - kQF - C::GW) * sizeof(typename C::S));
 }
 
 template <class C>
@@ -110,11 +118,15 @@ struct Node {
 // XCD has its own L2.
 constexpr uint32_t kXCD = 8;
 
-__device__ __forceinline__ bool node_of(const Geo &g, Node &d) {
+__device__ __forceinline__ uint32_t xcd_order() {
     const uint32_t b = blockIdx.x, nb = gridDim.x;
     const uint32_t xcd = b % kXCD, idx = b / kXCD;
     const uint32_t per = nb / kXCD, rem = nb % kXCD;
-    const uint32_t lb = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+// Node of thread threadIdx.x in logical block lb of a lattice.
+__device__ __forceinline__ bool node_at(const Geo &g, uint32_t lb, Node &d) {
     const uint32_t z = lb / g.gx;
     const uint32_t r = (lb - z * g.gx) * blockDim.x + threadIdx.x;
     d.z = static_cast<int>(z);
@@ -122,6 +134,10 @@ __device__ __forceinline__ bool node_of(const Geo &g, Node &d) {
     d.x = static_cast<int>(r) - d.y * g.N;
     d.n = static_cast<uint64_t>(d.z) * g.N2 + r;
     return r < g.N2;
+}
+
+__device__ __forceinline__ bool node_of(const Geo &g, Node &d) {
+    return node_at(g, xcd_order(), d);
 }
 
 // x - e outside the box?  (the upstream node of link e)
@@ -170,7 +186,7 @@ __device__ __forceinline__ typename C::R ld_f(const View &v, uint32_t off,
 template <class C>
 __device__ __forceinline__ typename C::R ld_g(const View &v, uint32_t off, int j,
                                               const Coef<typename C::R> &c) {
-    if (j == 0) return static_cast<typename C::R>(*reinterpret_cast<const typename C::W *>(v.base + off));
+    if (j < C::GW) return static_cast<typename C::R>(*reinterpret_cast<const typename C::W *>(v.base + off));
     return dec<C>(*reinterpret_cast<const typename C::S *>(v.base + off), c.isg);
 }
 template <class C>
@@ -182,7 +198,7 @@ template <class C>
 __device__ __forceinline__ void st_g(const View &v, uint32_t off, int j, typename C::R x,
                                      const Coef<typename C::R> &c) {
     char *p = const_cast<char *>(v.base) + off;
-    if (j == 0) *reinterpret_cast<typename C::W *>(p) = static_cast<typename C::W>(x);
+    if (j < C::GW) *reinterpret_cast<typename C::W *>(p) = static_cast<typename C::W>(x);
     else *reinterpret_cast<typename C::S *>(p) = enc<C>(x, c.sg);
 }
 
@@ -445,6 +461,102 @@ __global__ __launch_bounds__(256) void k_step(typename C::S *__restrict__ pop, G
     gather<C, CELL, SW>(pop, g, d, c, f, h);
     collide(f, h, c);
     scatter<C, CELL, SW>(pop, g, d, c, f, h);
+}
+
+// One step of many cavities in one launch.  Logical block lb belongs to the
+// last cavity whose first block is <= lb (binary search over the descriptor
+// table, wave-uniform); retired cavities' blocks return at once.  All
+// cavities of a batch share the storage parity.
+template <class C, bool SW>
+__global__ __launch_bounds__(256) void k_step_batch(const CavityDesc<typename C::R> *__restrict__ tab,
+                                                    int K) {
+    using R = typename C::R;
+    const uint32_t lb = xcd_order();
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].start <= lb) lo = mid;
+        else hi = mid - 1;
+    }
+    const CavityDesc<R> &D = tab[lo];
+    if (!D.active) return;
+    Node d;
+    if (!node_at(D.g, lb - D.start, d)) return;
+    typename C::S *pop = static_cast<typename C::S *>(D.pop);
+    R f[kQF], h[kQG];
+    if (D.cell == LBM_SIDE_HEATED) {
+        gather<C, LBM_SIDE_HEATED, SW>(pop, D.g, d, D.c, f, h);
+        collide(f, h, D.c);
+        scatter<C, LBM_SIDE_HEATED, SW>(pop, D.g, d, D.c, f, h);
+    } else {
+        gather<C, LBM_RAYLEIGH_BENARD, SW>(pop, D.g, d, D.c, f, h);
+        collide(f, h, D.c);
+        scatter<C, LBM_RAYLEIGH_BENARD, SW>(pop, D.g, d, D.c, f, h);
+    }
+}
+
+// Trilinear resampling of the fields (u, v, w, T) of an N^3 lattice onto M^3
+// node-centred points, FP32 output [4][M^3].  Per axis the samples are the
+// node values at (i + 1/2)/N and, beyond the first and last node, the wall
+// value at 0 or 1: u = v = w = 0 on every wall, T = T_w on the isothermal
+// walls; along the adiabatic axes T is held at the nearest node.
+__global__ __launch_bounds__(256) void k_resample(int N, int cell, double T_hot, double T_cold,
+                                                  const double *__restrict__ macro, int M,
+                                                  float *__restrict__ out) {
+    const uint64_t M3 = static_cast<uint64_t>(M) * M * M;
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= M3) return;
+    const int c3[3] = {static_cast<int>(t % M), static_cast<int>((t / M) % M),
+                       static_cast<int>(t / (static_cast<uint64_t>(M) * M))};
+    // per axis: the two samples (node index, or -1 / N for the low / high wall)
+    int i0[3], i1[3];
+    double w1[3];
+    for (int a = 0; a < 3; ++a) {
+        const double sidx = (c3[a] + 0.5) * N / M - 0.5;   // position in node units
+        int k = static_cast<int>(floor(sidx));
+        double fr = sidx - k;
+        if (k < 0) {            // between the low wall (-1/2) and node 0
+            i0[a] = -1; i1[a] = 0; w1[a] = (sidx + 0.5) / 0.5;
+        } else if (k >= N - 1) {  // between node N-1 and the high wall (N - 1/2)
+            i0[a] = N - 1; i1[a] = N; w1[a] = (sidx - (N - 1)) / 0.5;
+        } else {
+            i0[a] = k; i1[a] = k + 1; w1[a] = fr;
+        }
+    }
+    const uint64_t V = static_cast<uint64_t>(N) * N * N;
+    const int iso = cell == LBM_SIDE_HEATED ? 0 : 2;
+    for (int q = 0; q < 4; ++q) {
+        const double *phi = macro + (1 + q) * V;
+        double acc = 0.0;
+        for (int corner = 0; corner < 8; ++corner) {
+            int idx[3];
+            double wt = 1.0;
+            bool wall = false;
+            double wall_value = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const bool hi_side = (corner >> a) & 1;
+                int k = hi_side ? i1[a] : i0[a];
+                wt *= hi_side ? w1[a] : 1.0 - w1[a];
+                if (k < 0 || k >= N) {
+                    if (q < 3) {                 // velocity: no slip on every wall
+                        wall = true;
+                        wall_value = 0.0;
+                    } else if (a == iso) {       // temperature: isothermal wall
+                        wall = true;
+                        wall_value = k < 0 ? T_hot : T_cold;
+                    } else {                     // adiabatic axis: nearest node
+                        k = k < 0 ? 0 : N - 1;
+                    }
+                }
+                idx[a] = k;
+            }
+            if (wt == 0.0) continue;
+            const double val = wall ? wall_value
+                                    : phi[idx[0] + static_cast<uint64_t>(N) * (idx[1] + static_cast<uint64_t>(N) * idx[2])];
+            acc += wt * val;
+        }
+        out[q * M3 + t] = static_cast<float>(acc);
+    }
 }
 
 // f = f^eq(1, u) (Sec. 2.2), g = g^eq(T, u) (Sec. 2.3), canonical slots.
@@ -876,6 +988,58 @@ hipError_t launch_step(const lbm_t *h, int parity, hipStream_t s) {
     });
 }
 
+static_assert(sizeof(CavityDesc<double>) <= kMaxDescBytes, "descriptor table slot too small");
+static_assert(sizeof(CavityDesc<float>) <= kMaxDescBytes, "descriptor table slot too small");
+
+hipError_t build_batch_table(const lbm_batch *b, void *host_table, size_t *bytes) {
+    return with_codec(b->cav[0], [&](auto cd) {
+        using C = decltype(cd);
+        using R = typename C::R;
+        CavityDesc<R> *t = static_cast<CavityDesc<R> *>(host_table);
+        uint32_t start = 0;
+        for (int k = 0; k < b->K; ++k) {
+            const lbm_t *h = b->cav[k];
+            t[k].g = geo_for(h, b->block);
+            t[k].c = make_coef<R>(h);
+            t[k].pop = pop_ptr<C>(h);
+            t[k].cell = h->p.cell;
+            t[k].active = b->active[k];
+            t[k].start = start;
+            start += t[k].g.gx * t[k].g.N;
+        }
+        *bytes = sizeof(CavityDesc<R>) * b->K;
+        return hipSuccess;
+    });
+}
+
+uint32_t batch_blocks(const lbm_batch *b) {
+    uint32_t n = 0;
+    for (int k = 0; k < b->K; ++k) n += geo_for(b->cav[k], b->block).gx * b->cav[k]->geo.N;
+    return n;
+}
+
+hipError_t launch_step_batch(const lbm_batch *b, int parity, hipStream_t s) {
+    return with_codec(b->cav[0], [&](auto cd) {
+        using C = decltype(cd);
+        using R = typename C::R;
+        const auto *tab = reinterpret_cast<const CavityDesc<R> *>(static_cast<char *>(b->buf) + b->off_table);
+        const uint32_t nb = batch_blocks(b);
+        if (parity) k_step_batch<C, true><<<nb, b->block, 0, s>>>(tab, b->K);
+        else k_step_batch<C, false><<<nb, b->block, 0, s>>>(tab, b->K);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_resample(const lbm_t *h, int M, float *out, hipStream_t s) {
+    double *macro = dptr(h, h->L.off_macro);
+    hipError_t e = launch_macro(h, macro, nullptr, s);
+    if (e != hipSuccess) return e;
+    const uint64_t M3 = static_cast<uint64_t>(M) * M * M;
+    k_resample<<<static_cast<uint32_t>((M3 + 255) / 256), 256, 0, s>>>(
+        h->geo.N, h->p.cell, h->p.T_hot, h->p.T_cold, macro, M, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(const lbm_t *h, const double *uvwT, hipStream_t s) {
     return with_codec(h, [&](auto cd) {
         using C = decltype(cd);
@@ -1002,12 +1166,13 @@ Layout make_layout(int N, int storage) {
     const uint64_t N2 = static_cast<uint64_t>(N) * N;
     // sub-blocks of 32 KB per (moving) population, or one power of two
     // covering the whole plane when that is smaller
-    const uint64_t wide = storage == LBM_FP64 ? 8 : 4;   // width of the resting g_0
+    const uint64_t wide = storage == LBM_FP64 ? 8 : 4;   // width of the wide slots
+    const uint64_t nwide = storage == LBM_FP16S ? CF16::GW : 1;
     L.bbits = 0;
     while ((uint64_t{1} << L.bbits) * L.esize < 32768 && (uint64_t{1} << L.bbits) < N2) ++L.bbits;
     const uint64_t B = uint64_t{1} << L.bbits;
     const uint64_t nsub = (N2 + B - 1) / B;
-    L.node_bytes = (kNPop - 1) * L.esize + wide;
+    L.node_bytes = (kNPop - nwide) * L.esize + nwide * wide;
     L.sub = L.node_bytes * B;
     L.slab = nsub * L.sub;
     L.pop_bytes = L.slab * N;

@@ -46,6 +46,17 @@ struct Geo {
     uint32_t bbits, bmask;   // sub-block of 2^bbits nodes; bmask = 2^bbits - 1
 };
 
+// One cavity of a batch, as the batched step kernel sees it.
+template <class R>
+struct CavityDesc {
+    Geo g;
+    Coef<R> c;
+    void *pop;         // the cavity's population storage
+    int cell;          // LBM_SIDE_HEATED or LBM_RAYLEIGH_BENARD
+    int active;        // 0: retired, its blocks do nothing
+    uint32_t start;    // first logical block of the cavity in a batched launch
+};
+
 struct Layout {
     size_t esize = 0;        // bytes per stored moving population
     uint64_t node_bytes = 0; // storage bytes of one node's 26 populations
@@ -77,8 +88,26 @@ struct lbm {
     bool initialised = false;
     bool has_flux = false;   // a step was taken since the populations were set
     bool profiling = false;
+    bool in_batch = false;   // stepped only through its batch
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
+    std::string err;
+};
+
+// A batch of cavities advanced together (each one an ordinary handle whose
+// memory is a slice of the batch buffer).
+struct lbm_batch {
+    int K = 0;
+    int storage = 0;
+    int block = 256;
+    std::vector<lbm_t *> cav;
+    std::vector<int> active;
+    std::vector<double> last_res;      // last max |dT| of each cavity (inf before any check)
+    void *buf = nullptr;
+    bool own_buf = false;
+    size_t off_table = 0;    // device copy of the descriptor table
+    int parity = 0;
+    int64_t t = 0;
     std::string err;
 };
 
@@ -97,6 +126,14 @@ hipError_t launch_reset_acc(const lbm_t *h, hipStream_t s);
 // Residual against the snapshot into res[64..66], then snapshot := current.
 hipError_t launch_residual(const lbm_t *h, hipStream_t s);
 hipError_t launch_snapshot(const lbm_t *h, hipStream_t s);
+// Batches: host image of the descriptor table (returns its size in bytes),
+// total blocks of a batched launch, and the batched step.
+hipError_t build_batch_table(const lbm_batch *b, void *host_table, size_t *bytes);
+uint32_t batch_blocks(const lbm_batch *b);
+hipError_t launch_step_batch(const lbm_batch *b, int parity, hipStream_t s);
+// Fields (u, v, w, T) trilinearly resampled onto M^3 nodes, FP32 [4][M^3].
+hipError_t launch_resample(const lbm_t *h, int M, float *out, hipStream_t s);
+constexpr size_t kMaxDescBytes = 256;   // upper bound of sizeof(CavityDesc<double>)
 // Centreline maxima of u (over z) and w (over x) into res[kResPeak..+3].
 hipError_t launch_centerline(const lbm_t *h, hipStream_t s);
 

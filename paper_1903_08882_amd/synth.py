@@ -68,3 +68,21 @@ def rich_fields(N, seed=SEED0 + 100, u_amp=0.05, T_amp=0.5, rho_amp=1e-3):
 def population_noise(N, seed=SEED0 + 100, nq=26):
     """U[-1, 1) per (population, node): shape (nq, N, N, N)."""
     return np.stack([noise_field(N, seed, 16 + q, 1.0) for q in range(nq)])
+
+
+def sweep_cavities(K=64, seed=SEED0 + 3, sizes=(33, 49, 65), ra_range=(1e4, 1e7),
+                   prandtl=(0.71, 7.0)):
+    """K side-heated cavity set-ups for a training sweep: N uniform over
+    `sizes`, Ra log-uniform over `ra_range`, Pr uniform over `prandtl`, and a
+    noise seed per cavity.  Returns a list of dicts (N, Ra, Pr, seed)."""
+    a = (uniform(seed, 0, K) + 1.0) / 2.0          # [0, 1)
+    b = (uniform(seed, 1, K) + 1.0) / 2.0
+    c = (uniform(seed, 2, K) + 1.0) / 2.0
+    lo, hi = np.log10(ra_range[0]), np.log10(ra_range[1])
+    out = []
+    for k in range(K):
+        out.append({"N": int(sizes[min(int(a[k] * len(sizes)), len(sizes) - 1)]),
+                    "Ra": float(10.0 ** (lo + (hi - lo) * b[k])),
+                    "Pr": float(prandtl[min(int(c[k] * len(prandtl)), len(prandtl) - 1)]),
+                    "seed": int(seed * 1000 + k)})
+    return out

@@ -5,11 +5,11 @@ Population tolerance (per population, after the stated number of steps):
     |p_gpu - p_oracle| <= tol * max(|p_oracle|, floor_q)
 with floor_q = w_i for f and 0.5 * w^T_i for g (the size of a population at
 the largest |T| = 1/2), tol = 1e-5 for FP32 storage and arithmetic and 1e-12
-for FP64.  FP16 storage (moving populations as FP16 deviations, the resting
-g_0 as FP32, FP32 arithmetic) rounds every stored value to 11 significant
-bits, a relative error of at most 2^-11 of a value no larger than its floor;
-relaxation damps what accumulates in the non-conserved moments, so the error
-stays a few roundings: tol = 8 * 2^-11.
+for FP64.  FP16 storage (f as FP16 deviations, g as FP32, FP32 arithmetic)
+rounds every stored f to 11 significant bits, a relative error of at most
+2^-11 of a value no larger than its floor; relaxation damps what accumulates
+in the non-conserved moments, so the error stays a few roundings:
+tol = 8 * 2^-11.
 """
 import numpy as np
 import pytest
@@ -380,3 +380,142 @@ def test_centerline_peaks_against_oracle_fields(N):
     assert abs(got["w_max"] - w_line.max() / U) < 1e-12
     assert abs(got["w_max_x"] - (np.argmax(w_line) + 0.5) / N) < 1e-15
     assert abs(got["E"] - 0.5 * (m[1:4] ** 2).sum(0).mean() / U ** 2) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Batches of cavities, resampling, autotuner
+# --------------------------------------------------------------------------
+
+BATCH = [(9, 1e4, 0.71, 0), (12, 3e5, 7.0, 1), (17, 1e5, 0.71, 0), (7, 2e4, 7.0, 1)]
+
+
+def _rich_uvwT(N, k):
+    return synth.rich_fields(N, seed=synth.SEED0 + 300 + k)[1]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_batched_step_equals_single_handles_bitwise(storage):
+    """A batch advances each cavity exactly as its own handle would (same
+    kernels, same arithmetic): populations equal bit for bit, both parities."""
+    Ns, Ras, Prs, cells = zip(*BATCH)
+    opts = B.lbm_default_opts(U=0.1)
+    b = B.lbm_batch_create(Ns, Ras, Prs, cells, storage, opts)
+    singles = []
+    for k, (N, Ra, Pr, cell) in enumerate(BATCH):
+        f = dev(_rich_uvwT(N, k))
+        B.lbm_set_fields(B.lbm_batch_cavity(b, k), f)
+        h = B.lbm_create(N, Ra, Pr, cell, storage, opts)
+        B.lbm_set_fields(h, f)
+        singles.append(h)
+    for n in (1, 20):
+        B.lbm_batch_step(b, n)
+        for k, h in enumerate(singles):
+            B.lbm_step(h, n)
+            a = B.lbm_get_populations(B.lbm_batch_cavity(b, k)).cpu().numpy()
+            s = B.lbm_get_populations(h).cpu().numpy()
+            assert np.array_equal(a, s), (k, n)
+    with pytest.raises(B.LBMError) as e:
+        B.lbm_step(B.lbm_batch_cavity(b, 0), 1)
+    assert e.value.status == -6
+
+
+def test_batched_cavity_against_oracle():
+    Ns, Ras, Prs, cells = zip(*BATCH)
+    b = B.lbm_batch_create(Ns, Ras, Prs, cells, "fp64", B.lbm_default_opts(U=0.1))
+    for k, (N, Ra, Pr, cell) in enumerate(BATCH):
+        B.lbm_set_fields(B.lbm_batch_cavity(b, k), dev(_rich_uvwT(N, k)))
+    B.lbm_batch_step(b, 33)
+    for k, (N, Ra, Pr, cell) in enumerate(BATCH):
+        o = oracle.Oracle(N, Ra, Pr, cell, U=0.1)
+        o.init_fields(_rich_uvwT(N, k))
+        o.step(33)
+        got = B.lbm_get_populations(B.lbm_batch_cavity(b, k)).cpu().numpy()
+        assert_pop_close(got, o.pop, o.p, 1e-12, f"cavity {k}")
+
+
+def test_batch_retires_converged_cavities():
+    """Below-onset Rayleigh-Benard cavities of different sizes converge at
+    different times; a retired cavity is frozen at its own step count and
+    equals a lone handle run for that many steps."""
+    cav = [(6, 1e3, 0.71, 1), (10, 1e3, 0.71, 1), (8, 1e3, 7.0, 1)]
+    Ns, Ras, Prs, cells = zip(*cav)
+    b = B.lbm_batch_create(Ns, Ras, Prs, cells, "fp64")
+    for k, (N, *_rest) in enumerate(cav):
+        B.lbm_set_fields(B.lbm_batch_cavity(b, k), dev(synth.rest_with_noise(N)))
+    steps, res = B.lbm_batch_run_to_steady(b, 500, 1e-10, 80000)
+    say(f"batch steps {steps} residuals {res}")
+    assert all(r < 1e-10 for r in res) and len(set(steps)) > 1
+    for k, (N, Ra, Pr, cell) in enumerate(cav):
+        h = B.lbm_create(N, Ra, Pr, cell, "fp64")
+        B.lbm_set_fields(h, dev(synth.rest_with_noise(N)))
+        B.lbm_step(h, steps[k])
+        a = B.lbm_get_populations(B.lbm_batch_cavity(b, k)).cpu().numpy()
+        assert np.array_equal(a, B.lbm_get_populations(h).cpu().numpy()), k
+
+
+def _resample_reference(m, M, iso, T_hot, T_cold):
+    """Trilinear resampling with wall anchors, written out per target node."""
+    N = m.shape[1]
+    out = np.zeros((4, M, M, M))
+    xs = (np.arange(M) + 0.5) * N / M - 0.5
+    for q in range(4):
+        phi = m[1 + q]                          # [z][y][x]
+        for kz in range(M):
+            for ky in range(M):
+                for kx in range(M):
+                    s = (xs[kx], xs[ky], xs[kz])
+                    acc = 0.0
+                    for corner in range(8):
+                        idx, wt, wall, wv = [], 1.0, False, 0.0
+                        for a in range(3):
+                            i0 = int(np.floor(s[a]))
+                            if i0 < 0:
+                                lo, hi, t = -1, 0, (s[a] + 0.5) / 0.5
+                            elif i0 >= N - 1:
+                                lo, hi, t = N - 1, N, (s[a] - (N - 1)) / 0.5
+                            else:
+                                lo, hi, t = i0, i0 + 1, s[a] - i0
+                            up = (corner >> a) & 1
+                            k = hi if up else lo
+                            wt *= t if up else 1 - t
+                            if k < 0 or k >= N:
+                                if q < 3:
+                                    wall, wv = True, 0.0
+                                elif a == iso:
+                                    wall, wv = True, (T_hot if k < 0 else T_cold)
+                                else:
+                                    k = 0 if k < 0 else N - 1
+                            idx.append(k)
+                        if wt == 0:
+                            continue
+                        acc += wt * (wv if wall else phi[idx[2], idx[1], idx[0]])
+                    out[q, kz, ky, kx] = acc
+    return out
+
+
+@pytest.mark.parametrize("cell,N,M", [(0, 9, 13), (1, 12, 5), (0, 8, 8)])
+def test_resample_fields_against_definition(cell, N, M):
+    pr = Pair(N, 1e5, 0.71, cell, "fp64", U=0.1)
+    pr.init_rich()
+    pr.step(5)
+    got = B.lbm_resample_fields(pr.h, M).cpu().numpy().reshape(4, M, M, M)
+    m = pr.o.macro().reshape(5, N, N, N)
+    want = _resample_reference(m, M, 0 if cell == 0 else 2, pr.p.T_hot, pr.p.T_cold)
+    assert np.abs(got - want).max() < 1e-6
+
+
+def test_autotune_picks_a_candidate_and_caches_it():
+    h = B.lbm_create(65, 1e6, 0.71, "side_heated", "fp32")
+    B.lbm_set_fields(h, dev(synth.rest_with_noise(65)))
+    blk, ms = B.lbm_autotune(h, 10)
+    assert blk in (64, 128, 192, 256) and ms > 0
+    h2 = B.lbm_create(65, 1e6, 0.71, "side_heated", "fp32")
+    B.lbm_set_fields(h2, dev(synth.rest_with_noise(65)))
+    blk2, ms2 = B.lbm_autotune(h2, 10)
+    assert blk2 == blk and ms2 == 0.0
+    Ns, Ras, Prs, cells = zip(*BATCH)
+    b = B.lbm_batch_create(Ns, Ras, Prs, cells, "fp32", B.lbm_default_opts(U=0.1))
+    for k, (N, *_r) in enumerate(BATCH):
+        B.lbm_set_fields(B.lbm_batch_cavity(b, k), dev(_rich_uvwT(N, k)))
+    bb, bms = B.lbm_batch_autotune(b, 6)
+    assert bb in (64, 128, 192, 256) and bms > 0

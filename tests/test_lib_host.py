@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, s), s
     # and the binding wraps each of them under the same name
     for s in syms:
-        assert hasattr(B, s) or s in ("lbm_last_error", "lbm_strerror"), s
+        assert hasattr(B, s) or s in ("lbm_last_error", "lbm_strerror", "lbm_batch_last_error"), s
 
 
 def test_binding_signature_table_covers_header():
@@ -74,13 +74,14 @@ def test_parameter_errors():
 
 
 def test_state_bytes_cover_populations_and_scratch():
-    for N, st, es in [(33, "fp32", 4), (257, "fp32", 4), (257, "fp64", 8), (129, "fp16s", 2)]:
+    for N, st, es, nb in [(33, "fp32", 4, 104), (257, "fp32", 4, 104), (257, "fp64", 8, 208),
+                          (129, "fp16s", 2, 66)]:
         b = B.lbm_state_bytes(N, st)
-        pops = 26 * N ** 3 * es
+        pops = nb * N ** 3
         scratch = (5 + 4) * N ** 3 * 8
         # node blocks pad each z-plane to whole sub-blocks: at most 2x for
         # lattices smaller than one sub-block, at most one sub-block per plane
-        sub = 32768 // es * 26 * es
+        sub = 32768 // es * nb
         pad = min(pops, N * sub)
         assert pops + scratch <= b <= pops + pad + scratch + 64 * N * N * 8 + (1 << 20)
 
