@@ -73,7 +73,8 @@ enum lbm_status {
     LBM_ENOMEM = -3,    /* caller buffer too small, or allocation failed      */
     LBM_EDEVICE = -4,   /* HIP runtime error (text in lbm_last_error)         */
     LBM_EDIVERGED = -5, /* a reduction came back NaN or infinite              */
-    LBM_ESTATE = -6     /* call not valid in the handle's current state       */
+    LBM_ESTATE = -6,    /* call not valid in the handle's current state       */
+    LBM_EIO = -7        /* checkpoint file missing, short, corrupt or foreign */
 };
 
 /* Raw observables (lattice units, FP64), indices of the LBM_NRAW vector.
@@ -221,6 +222,24 @@ LBM_API int lbm_reset_averages(lbm_t *h, void *stream);
  * Synchronises stream.  Any output pointer may be NULL. */
 LBM_API int lbm_residual(lbm_t *h, void *stream, double *max_dT, double *rel_L1_T,
                  double *rel_L2_u);
+
+/* Checkpoint and restart of one cavity (not part of the paper's method; long
+ * Rayleigh-Benard averaging runs need it).  lbm_save writes, to the host file
+ * at path, a header (N, cell, storage, Ra, Pr, U, T0, step count, AA parity,
+ * sample count), the population storage exactly as it sits in device memory,
+ * the FP64 time-average accumulators and a 64-bit FNV-1a checksum of all of
+ * it; it synchronises stream.  lbm_load reads such a file into a handle
+ * created with the same N, cell, storage, Ra, Pr, U and T0 (LBM_EINVAL
+ * otherwise), restores the step count, the parity and the time averages, and
+ * records the loaded state as the residual reference; the wall flux of the
+ * step before the save is not kept (observables need one step first, as after
+ * lbm_set_populations).  Stepping a loaded handle continues bit for bit as
+ * the saved one would have.  LBM_EIO for a file that cannot be opened, read
+ * or written, is short, or fails its magic or checksum; LBM_ESTATE when
+ * saving a handle whose populations were never set, or loading into a
+ * cavity of a batch. */
+LBM_API int lbm_save(lbm_t *h, const char *path, void *stream);
+LBM_API int lbm_load(lbm_t *h, const char *path, void *stream);
 
 /* Steady-state driver (Sec. 3 criterion, with the maximum change of T as the
  * stopping measure): repeat { lbm_step(check_every); lbm_residual } until

@@ -193,20 +193,23 @@ def flatten(p, ch=(16, 32, 64)):
                            for name, _ in param_shapes(ch)])
 
 
-def forward(p, cond, M, ch=(16, 32, 64), X0=None):
+def forward(p, cond, M, ch=(16, 32, 64), X0=None, rnd=None):
     """Network output [B, M, M, M, 8] for conditioning rows cond [B, 2], and
-    the cache the backward pass needs."""
+    the cache the backward pass needs.  With rnd (e.g. bf16_round) every
+    convolution operand (input activation and weights) and every stored
+    activation is passed through rnd, as reduced-precision kernels store them;
+    rnd=None is the exact network."""
+    rnd = rnd or (lambda a: a)
     cond = np.atleast_2d(np.asarray(cond, dtype=np.float64))
-    B = cond.shape[0]
-    X0 = features(M) if X0 is None else X0
-    cache = {"cond": cond, "X0": X0}
+    X0 = rnd(features(M) if X0 is None else X0)
+    cache = {"cond": cond, "X0": X0, "rnd": rnd}
 
     def block(name, X):
-        Z = conv3d(X, p[name + ".W"])
+        Z = conv3d(X, rnd(p[name + ".W"]))
         sc, sh = film(cond, p[name + ".Gw"], p[name + ".Gb"], p[name + ".Bw"], p[name + ".Bb"])
         Y = Z * sc[:, None, None, None, :] + sh[:, None, None, None, :]
         cache[name] = (X, Z, Y, sc)
-        return silu(Y)
+        return rnd(silu(Y))
 
     a = block("E1a", X0)
     s1 = block("E1b", a)
@@ -214,9 +217,9 @@ def forward(p, cond, M, ch=(16, 32, 64), X0=None):
     s2 = block("E2b", a)
     a = block("E3a", restrict(s2))
     s3 = block("E3b", a)
-    a = block("D2", np.concatenate([prolong(s3), s2], axis=-1))
-    a = block("D1", np.concatenate([prolong(a), s1], axis=-1))
-    out = conv3d(a, p["OUT.W"]) + p["OUT.b"]
+    a = block("D2", np.concatenate([rnd(prolong(s3)), s2], axis=-1))
+    a = block("D1", np.concatenate([rnd(prolong(a)), s1], axis=-1))
+    out = conv3d(a, rnd(p["OUT.W"])) + p["OUT.b"]
     cache["OUT"] = a
     cache["shapes"] = (s1.shape, s2.shape, s3.shape)
     return out, cache
@@ -224,15 +227,19 @@ def forward(p, cond, M, ch=(16, 32, 64), X0=None):
 
 def backward(p, cache, dout, ch=(16, 32, 64)):
     """Gradients of a scalar loss with respect to every parameter, given the
-    loss's gradient dout [B, M, M, M, 8] with respect to the output."""
+    loss's gradient dout [B, M, M, M, 8] with respect to the output.  With the
+    forward pass's rnd, the convolution operands of the backward pass (the
+    output gradient, each dZ, the weights) are rounded the same way."""
     cond = cache["cond"]
+    rnd = cache["rnd"]
     g = {}
     c1, c2, c3 = ch
     s1s, s2s, s3s = cache["shapes"]
     a = cache["OUT"]
-    g["OUT.W"] = conv3d_bwd_weight(a, dout)
+    dr = rnd(dout)
+    g["OUT.W"] = conv3d_bwd_weight(a, dr)
     g["OUT.b"] = dout.sum(axis=(0, 1, 2, 3))
-    da = conv3d_bwd_data(dout, p["OUT.W"])
+    da = conv3d_bwd_data(dr, rnd(p["OUT.W"]))
 
     def block_bwd(name, da, need_dx=True):
         X, Z, Y, sc = cache[name]
@@ -243,9 +250,9 @@ def backward(p, cache, dout, ch=(16, 32, 64)):
         g[name + ".Gb"] = dsc.sum(axis=0)
         g[name + ".Bw"] = dsh.T @ cond
         g[name + ".Bb"] = dsh.sum(axis=0)
-        dZ = dY * sc[:, None, None, None, :]
+        dZ = rnd(dY * sc[:, None, None, None, :])
         g[name + ".W"] = conv3d_bwd_weight(X, dZ)
-        return conv3d_bwd_data(dZ, p[name + ".W"]) if need_dx else None
+        return conv3d_bwd_data(dZ, rnd(p[name + ".W"])) if need_dx else None
 
     dX = block_bwd("D1", da)                        # [.., c2 + c1]
     ds1 = dX[..., c2:].copy()
@@ -289,3 +296,43 @@ def bf16_round(a):
     u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
     return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def upsample_fields(pred, M, N, cell, U, T_hot, T_cold):
+    """Fields on the node-centred M^3 grid (pred [M, M, M, >=4]: u/U, v/U, w/U,
+    T*) trilinearly interpolated at the N^3 lattice nodes (i + 1/2)/N, in
+    lattice units, [4, N, N, N].  Per axis the samples are the M nodes and,
+    half a spacing beyond the outermost ones, the walls: velocity 0 on every
+    wall; T* = +1/2 at the low and -1/2 at the high isothermal wall (axis x
+    for side-heated, cell 0; z for Rayleigh-Benard), the nearest node's T*
+    across an adiabatic wall."""
+    ext = np.zeros((M + 2,) * 3 + (4,))
+    ext[1:-1, 1:-1, 1:-1] = pred[..., :4]
+    # temperature beyond adiabatic walls: the nearest node (edges and corners too)
+    T = np.pad(pred[..., 3], 1, mode="edge")
+    iso = 2 if cell == 0 else 0                   # array axis of the isothermal walls (z, y, x order)
+    lo = [slice(None)] * 3
+    hi = [slice(None)] * 3
+    lo[iso], hi[iso] = 0, M + 1
+    T[tuple(lo)] = 0.5
+    T[tuple(hi)] = -0.5
+    ext[..., 3] = T
+    # sample positions in units of the node spacing, with the walls at -1/2 and M - 1/2
+    pos = [-0.5] + list(range(M)) + [M - 0.5]
+    s = (np.arange(N) + 0.5) / N * M - 0.5
+    idx = np.clip(np.searchsorted(pos, s, side="right") - 1, 0, M)
+    w = (s - np.take(pos, idx)) / (np.take(pos, idx + 1) - np.take(pos, idx))
+    out = np.zeros((4, N, N, N))
+    for cz in (0, 1):
+        wz = w if cz else 1 - w
+        for cy in (0, 1):
+            wy = w if cy else 1 - w
+            for cx in (0, 1):
+                wx = w if cx else 1 - w
+                vals = ext[np.ix_(idx + cz, idx + cy, idx + cx)]          # [N, N, N, 4]
+                wt = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
+                out += np.moveaxis(vals, -1, 0) * wt[None]
+    Tm, dT = 0.5 * (T_hot + T_cold), T_hot - T_cold
+    out[:3] *= U
+    out[3] = Tm + dT * out[3]
+    return out

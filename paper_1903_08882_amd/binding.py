@@ -29,7 +29,7 @@ OBS_NAMES = ["Nu_hot", "Nu_cold", "Nu_hot_mid", "Nu_cold_mid", "Nu_hot_fd", "Nu_
              "Nu_kin", "Nu_th", "E", "rms_drho", "mean_T", "rms_div"]
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ERANGE", -3: "LBM_ENOMEM", -4: "LBM_EDEVICE",
-          -5: "LBM_EDIVERGED", -6: "LBM_ESTATE"}
+          -5: "LBM_EDIVERGED", -6: "LBM_ESTATE", -7: "LBM_EIO"}
 
 
 class LBMError(RuntimeError):
@@ -85,6 +85,8 @@ _SIG = {
     "lbm_residual": (ctypes.c_int, [_P, _P, _D, _D, _D]),
     "lbm_run_to_steady": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, _P,
                                          ctypes.POINTER(ctypes.c_int64), _D, _D, ctypes.c_int64]),
+    "lbm_save": (ctypes.c_int, [_P, ctypes.c_char_p, _P]),
+    "lbm_load": (ctypes.c_int, [_P, ctypes.c_char_p, _P]),
     "lbm_centerline_peaks": (ctypes.c_int, [_P, _P, _D]),
     "lbm_resample_fields": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "lbm_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
@@ -291,6 +293,16 @@ def lbm_run_to_steady(h, check_every=1000, tol_max_dT=1e-8, max_steps=10**6, str
                                    hist if history_len else None, int(history_len)), h.ptr)
     nchk = -(-steps.value // int(check_every))
     return steps.value, r.value, list(hist)[:min(history_len, nchk)]
+
+
+def lbm_save(h, path, stream=None):
+    """Write the handle's state to the checkpoint file `path`."""
+    _check(lib().lbm_save(h.ptr, os.fsencode(path), _stream(stream)), h.ptr)
+
+
+def lbm_load(h, path, stream=None):
+    """Restore a checkpoint written by lbm_save into a handle with the same set-up."""
+    _check(lib().lbm_load(h.ptr, os.fsencode(path), _stream(stream)), h.ptr)
 
 
 def lbm_centerline_peaks(h, stream=None):

@@ -1,6 +1,7 @@
 // api.hip -- host side of the C ABI declared in include/lbm.h: parameter
 // derivation (Sec. 2.1-2.3 of Xu, Shi & Xi 2019), argument checks, the
 // device-memory layout, the step loop and the synchronising queries.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -8,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <vector>
 
 #include "lbm_internal.h"
 
@@ -369,6 +371,147 @@ int lbm_run_to_steady(lbm_t *h, int64_t check_every, double tol_max_dT, int64_t 
     return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checkpoint file: CkptHeader, the population storage bytes, the result block
+// (kResDoubles doubles), then the FNV-1a 64 hash of everything before it.
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t N, cell, storage, parity, reserved;
+    int64_t t, samples;
+    double Ra, Pr, U, T0;
+    uint64_t pop_bytes, res_doubles;
+};
+constexpr char kCkptMagic[8] = {'P', '1', '9', '0', '3', 'L', 'B', 'M'};
+constexpr size_t kCkptChunk = size_t{64} << 20;
+
+struct Fnv {
+    uint64_t h = 0xcbf29ce484222325ull;
+    void add(const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+    }
+};
+
+struct File {
+    FILE *f = nullptr;
+    ~File() { if (f) std::fclose(f); }
+};
+
+bool same_params(const CkptHeader &c, const lbm_t *h) {
+    return c.N == h->p.N && c.cell == h->p.cell && c.storage == h->storage && c.Ra == h->p.Ra &&
+           c.Pr == h->p.Pr && c.U == h->p.U && c.T0 == h->p.T0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_save(lbm_t *h, const char *path, void *stream) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!path) return fail(h, LBM_EINVAL, "path is NULL");
+    hipStream_t s = as_stream(stream);
+    CkptHeader c{};
+    std::memcpy(c.magic, kCkptMagic, 8);
+    c.version = 1;
+    c.N = h->p.N;
+    c.cell = h->p.cell;
+    c.storage = h->storage;
+    c.parity = h->parity;
+    c.t = h->t;
+    c.samples = h->samples;
+    c.Ra = h->p.Ra;
+    c.Pr = h->p.Pr;
+    c.U = h->p.U;
+    c.T0 = h->p.T0;
+    c.pop_bytes = h->L.pop_bytes;
+    c.res_doubles = lbmk::kResDoubles;
+    File f;
+    if (!(f.f = std::fopen(path, "wb"))) return fail(h, LBM_EIO, "cannot open %s for writing", path);
+    Fnv sum;
+    auto put = [&](const void *p, size_t n) {
+        sum.add(p, n);
+        return std::fwrite(p, 1, n, f.f) == n;
+    };
+    if (!put(&c, sizeof c)) return fail(h, LBM_EIO, "short write to %s", path);
+    std::vector<char> host(std::min<size_t>(kCkptChunk, h->L.pop_bytes));
+    const char *dev = static_cast<const char *>(h->buf) + h->L.off_pop;
+    for (size_t o = 0; o < h->L.pop_bytes; o += host.size()) {
+        const size_t n = std::min(host.size(), h->L.pop_bytes - o);
+        hipError_t e = hipMemcpyAsync(host.data(), dev + o, n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "reading populations");
+        if (!put(host.data(), n)) return fail(h, LBM_EIO, "short write to %s", path);
+    }
+    double res[lbmk::kResDoubles];
+    if ((rc = read_res(h, s, 0, lbmk::kResDoubles, res)) != LBM_OK) return rc;
+    if (!put(res, sizeof res)) return fail(h, LBM_EIO, "short write to %s", path);
+    const uint64_t hash = sum.h;
+    if (std::fwrite(&hash, 1, sizeof hash, f.f) != sizeof hash || std::fflush(f.f) != 0)
+        return fail(h, LBM_EIO, "short write to %s", path);
+    return LBM_OK;
+}
+
+int lbm_load(lbm_t *h, const char *path, void *stream) {
+    if (!h) return LBM_EINVAL;
+    if (!path) return fail(h, LBM_EINVAL, "path is NULL");
+    if (h->in_batch) return fail(h, LBM_ESTATE, "cannot load into a cavity of a batch");
+    hipStream_t s = as_stream(stream);
+    File f;
+    if (!(f.f = std::fopen(path, "rb"))) return fail(h, LBM_EIO, "cannot open %s", path);
+    CkptHeader c{};
+    if (std::fread(&c, 1, sizeof c, f.f) != sizeof c || std::memcmp(c.magic, kCkptMagic, 8) != 0 ||
+        c.version != 1)
+        return fail(h, LBM_EIO, "%s is not a checkpoint of this library", path);
+    if (!same_params(c, h))
+        return fail(h, LBM_EINVAL, "checkpoint %s was written for other N, cell, storage or parameters", path);
+    if (c.pop_bytes != h->L.pop_bytes || c.res_doubles != lbmk::kResDoubles || c.parity < 0 ||
+        c.parity > 1 || c.t < 0 || c.samples < 0)
+        return fail(h, LBM_EIO, "checkpoint %s has an inconsistent header", path);
+    // first pass: the checksum, before anything reaches the device
+    std::vector<char> host(std::min<size_t>(kCkptChunk, c.pop_bytes));
+    double res[lbmk::kResDoubles];
+    Fnv sum;
+    sum.add(&c, sizeof c);
+    for (size_t o = 0; o < c.pop_bytes; o += host.size()) {
+        const size_t n = std::min<size_t>(host.size(), c.pop_bytes - o);
+        if (std::fread(host.data(), 1, n, f.f) != n) return fail(h, LBM_EIO, "%s is truncated", path);
+        sum.add(host.data(), n);
+    }
+    uint64_t hash = 0;
+    if (std::fread(res, 1, sizeof res, f.f) != sizeof res ||
+        std::fread(&hash, 1, sizeof hash, f.f) != sizeof hash)
+        return fail(h, LBM_EIO, "%s is truncated", path);
+    sum.add(res, sizeof res);
+    if (hash != sum.h) return fail(h, LBM_EIO, "checksum mismatch in %s", path);
+    // second pass: copy to the device
+    if (std::fseek(f.f, static_cast<long>(sizeof c), SEEK_SET) != 0)
+        return fail(h, LBM_EIO, "cannot seek in %s", path);
+    char *dev = static_cast<char *>(h->buf) + h->L.off_pop;
+    for (size_t o = 0; o < c.pop_bytes; o += host.size()) {
+        const size_t n = std::min<size_t>(host.size(), c.pop_bytes - o);
+        if (std::fread(host.data(), 1, n, f.f) != n) return fail(h, LBM_EIO, "%s is truncated", path);
+        hipError_t e = hipMemcpyAsync(dev + o, host.data(), n, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "writing populations");
+    }
+    double *dres = reinterpret_cast<double *>(static_cast<char *>(h->buf) + h->L.off_res);
+    hipError_t e = hipMemcpyAsync(dres, res, sizeof res, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "writing the result block");
+    h->parity = c.parity;
+    h->t = c.t;
+    h->samples = c.samples;
+    h->has_flux = false;
+    h->initialised = true;
+    if ((e = lbmk::launch_snapshot(h, s)) != hipSuccess) return hip_fail(h, e, "snapshot");
+    return LBM_OK;
+}
+
 int lbm_centerline_peaks(lbm_t *h, void *stream, double out[5]) {
     int rc = require_init(h);
     if (rc) return rc;
@@ -721,6 +864,7 @@ const char *lbm_strerror(int status) {
     case LBM_EDEVICE: return "HIP runtime error";
     case LBM_EDIVERGED: return "non-finite result (diverged)";
     case LBM_ESTATE: return "call not valid in the current state";
+    case LBM_EIO: return "checkpoint file missing, short, corrupt or foreign";
     }
     return "unknown status";
 }

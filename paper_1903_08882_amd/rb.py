@@ -1,0 +1,145 @@
+"""Rayleigh-Benard cube: time-averaged Nusselt and Reynolds numbers and
+dissipation rates (Sec. 4, Table 4), in one storage format or several.
+
+    python -m paper_1903_08882_amd.rb --N 257 --Ra 1e7 --Pr 0.7 --storage fp32 fp16s
+
+For each storage format: fluid at rest with seeded temperature noise, a
+transient of at least `--min-transient` free-fall times, run in blocks of
+`--block-tf` free-fall times until the block means of Nu_vol of two successive
+blocks differ by less than `--settle` (relative), then `--avg-steps` steps of
+averaging split into `--sub` equal sub-blocks, the observables sampled every
+`--sample-every` steps and accumulated in FP64 on the GPU.  Reports the means,
+the standard error of the sub-block means, and the paper's values for the same
+(Ra, Pr) as context (the paper's grids and averaging times differ).  One JSON
+line per storage format, then a comparison line when there are several.
+"""
+import argparse
+import json
+import math
+import time
+
+import torch
+
+from . import binding as B
+from . import synth
+
+# Sec. 4, Table 4: Re_rms, Re_w, Nu_vol, Nu_wall, Nu_kin, Nu_th.
+PAPER = {
+    (1e6, 0.7): (208.80, 145.58, 8.33, 8.35, 8.24, 8.26),
+    (3e6, 0.7): (357.11, 249.96, 11.46, 11.48, 11.35, 11.37),
+    (1e7, 0.7): (654.86, 454.92, 16.22, 16.27, 16.07, 16.10),
+    (1e6, 7.0): (26.13, 20.26, 8.49, 8.52, 8.46, 8.44),
+    (3e6, 7.0): (44.56, 33.65, 11.12, 11.14, 11.08, 11.06),
+    (1e7, 7.0): (86.41, 65.71, 16.16, 16.19, 16.11, 16.03),
+}
+KEYS = ["Re_rms", "Re_w", "Nu_vol", "Nu_wall", "Nu_kin", "Nu_th", "eps_u", "eps_T",
+        "Nu_hot", "Nu_cold", "Nu_hot_fd", "Nu_cold_fd"]
+
+
+def _summary(params, raw):
+    nd = B.lbm_nondimensional(params, raw)
+    nd["Nu_wall"] = 0.5 * (nd["Nu_hot"] + nd["Nu_cold"])
+    return {k: nd[k] for k in KEYS}
+
+
+def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, settle=0.01,
+             max_transient_tf=400.0, avg_steps=100_000, sub=10, sample_every=100, log=print):
+    opts = B.lbm_default_opts(sample_every=sample_every)
+    h = B.lbm_create(N, Ra, Pr, "rayleigh_benard", storage, opts)
+    p = B.lbm_get_params(h)
+    tf = p.H / p.U                                   # steps per free-fall time
+    blk = max(sample_every, int(round(block_tf * tf / sample_every)) * sample_every)
+    B.lbm_set_fields(h, torch.from_numpy(synth.rest_with_noise(N, seed).reshape(-1)).cuda())
+    t0 = time.perf_counter()
+    steps, prev, trans = 0, None, []
+    while True:
+        B.lbm_reset_averages(h)
+        B.lbm_step(h, blk)
+        raw, _ = B.lbm_averages(h)
+        steps += blk
+        nu = _summary(p, raw)["Nu_vol"]
+        if not math.isfinite(nu):
+            raise B.LBMError(-5, f"Nu_vol not finite after {steps} steps")
+        trans.append(nu)
+        d = abs(nu - prev) / abs(nu) if prev is not None else float("inf")
+        log(f"# {storage} transient {steps} steps ({steps / tf:.0f} t_f): block Nu_vol {nu:.4f} "
+            f"(change {d:.2%})  {time.perf_counter() - t0:.0f} s")
+        prev = nu
+        if steps >= min_transient_tf * tf and d < settle:
+            break
+        if steps >= max_transient_tf * tf:
+            log(f"# {storage}: block means still moving after {max_transient_tf:.0f} t_f")
+            break
+    transient = steps
+    per = max(sample_every, (avg_steps // sub) // sample_every * sample_every)
+    subs, raws = [], []
+    ta = time.perf_counter()
+    for i in range(sub):
+        B.lbm_reset_averages(h)
+        B.lbm_step(h, per)
+        raw, cnt = B.lbm_averages(h)
+        raws.append(raw)
+        subs.append(_summary(p, raw))
+        log(f"# {storage} averaging {i + 1}/{sub}: Nu_vol {subs[-1]['Nu_vol']:.4f} "
+            f"Re_rms {subs[-1]['Re_rms']:.2f}  {time.perf_counter() - t0:.0f} s")
+    torch.cuda.synchronize()
+    wall_avg = time.perf_counter() - ta
+    mean_raw = [sum(r[j] for r in raws) / sub for j in range(len(raws[0]))]
+    mean = _summary(p, mean_raw)
+    se = {k: (math.sqrt(sum((s[k] - sum(t[k] for t in subs) / sub) ** 2 for s in subs)
+                        / (sub - 1) / sub) if sub > 1 else float("nan")) for k in KEYS}
+    out = {"N": N, "Ra": Ra, "Pr": Pr, "storage": storage, "seed": seed,
+           "steps_per_tf": tf, "transient_steps": transient, "transient_block_Nu_vol": trans,
+           "avg_steps": per * sub, "avg_tf": per * sub / tf, "samples": per * sub // sample_every,
+           "mean": mean, "stderr": se,
+           "MLUPS_averaging": N ** 3 * per * sub / wall_avg / 1e6,
+           "wall_s": time.perf_counter() - t0}
+    ref = PAPER.get((Ra, Pr))
+    if ref:
+        out["paper"] = dict(zip(KEYS[:6], ref))
+    B.lbm_destroy(h)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--N", type=int, default=257)
+    ap.add_argument("--Ra", type=float, default=1e7)
+    ap.add_argument("--Pr", type=float, default=0.7)
+    ap.add_argument("--storage", nargs="+", default=["fp32", "fp16s"],
+                    choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--seed", type=int, default=None,
+                    help="noise seed (default: base seed + 2 + case index)")
+    ap.add_argument("--min-transient", type=float, default=100.0, help="free-fall times")
+    ap.add_argument("--max-transient", type=float, default=400.0, help="free-fall times")
+    ap.add_argument("--block-tf", type=float, default=20.0)
+    ap.add_argument("--settle", type=float, default=0.01)
+    ap.add_argument("--avg-steps", type=int, default=100_000)
+    ap.add_argument("--sub", type=int, default=10)
+    ap.add_argument("--sample-every", type=int, default=100)
+    a = ap.parse_args()
+    cases = [(1e6, 0.7), (3e6, 0.7), (1e7, 0.7), (1e6, 7.0), (3e6, 7.0), (1e7, 7.0)]
+    seed = a.seed
+    if seed is None:
+        idx = next((i for i, c in enumerate(cases) if c == (a.Ra, a.Pr)), 0)
+        seed = synth.SEED0 + 2 + idx
+    res = []
+    for s in a.storage:
+        r = run_case(a.N, a.Ra, a.Pr, s, seed, a.min_transient, a.block_tf, a.settle,
+                     a.max_transient, a.avg_steps, a.sub, a.sample_every,
+                     log=lambda m: print(m, flush=True))
+        res.append(r)
+        print(json.dumps(r), flush=True)
+    if len(res) > 1:
+        base = res[0]
+        cmp = {}
+        for r in res[1:]:
+            cmp[r["storage"]] = {
+                k: {"rel_diff": (r["mean"][k] - base["mean"][k]) / base["mean"][k],
+                    "combined_stderr_rel": math.hypot(r["stderr"][k], base["stderr"][k])
+                    / abs(base["mean"][k])} for k in KEYS[:8]}
+        print(json.dumps({"compare_against": base["storage"], "diff": cmp}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -519,3 +519,51 @@ def test_autotune_picks_a_candidate_and_caches_it():
         B.lbm_set_fields(B.lbm_batch_cavity(b, k), dev(_rich_uvwT(N, k)))
     bb, bms = B.lbm_batch_autotune(b, 6)
     assert bb in (64, 128, 192, 256) and bms > 0
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_checkpoint_restart_continues_bit_for_bit(storage, tmp_path):
+    """Save after an odd number of steps (swapped AA parity) with time averages
+    running, load into a fresh handle, and step both: populations and averages
+    agree exactly.  Foreign, mismatched and corrupted files are refused."""
+    N = 13
+    say(f"[checkpoint] N={N} storage={storage}")
+    opts = B.lbm_default_opts(sample_every=5)
+    a = B.lbm_create(N, 1e6, 0.71, "side_heated", storage, opts)
+    rho, uvwT = synth.rich_fields(N)
+    B.lbm_set_fields(a, dev(uvwT))
+    B.lbm_step(a, 37)
+    path = str(tmp_path / "a.ckpt")
+    B.lbm_save(a, path)
+    b = B.lbm_create(N, 1e6, 0.71, "side_heated", storage, opts)
+    B.lbm_load(b, path)
+    assert B.lbm_time(b) == 37
+    B.lbm_step(a, 41)
+    B.lbm_step(b, 41)
+    pa = B.lbm_get_populations(a).cpu().numpy()
+    pb = B.lbm_get_populations(b).cpu().numpy()
+    assert np.array_equal(pa, pb)
+    ra, ca = B.lbm_averages(a)
+    rb, cb = B.lbm_averages(b)
+    assert ca == cb == (37 + 41) // 5 and ra == rb
+    assert B.lbm_observables_raw(a) == B.lbm_observables_raw(b)
+    # other parameters, other size, corrupted payload, missing file
+    c = B.lbm_create(N, 2e6, 0.71, "side_heated", storage, opts)
+    with pytest.raises(B.LBMError, match="LBM_EINVAL"):
+        B.lbm_load(c, path)
+    d = B.lbm_create(N + 1, 1e6, 0.71, "side_heated", storage, opts)
+    with pytest.raises(B.LBMError, match="LBM_EINVAL"):
+        B.lbm_load(d, path)
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0x40
+    bad = str(tmp_path / "bad.ckpt")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(B.LBMError, match="LBM_EIO"):
+        B.lbm_load(b, bad)
+    with pytest.raises(B.LBMError, match="LBM_EIO"):
+        B.lbm_load(b, str(tmp_path / "missing.ckpt"))
+    # the refused loads left b as it was
+    B.lbm_step(a, 3)
+    B.lbm_step(b, 3)
+    assert np.array_equal(B.lbm_get_populations(a).cpu().numpy(),
+                          B.lbm_get_populations(b).cpu().numpy())

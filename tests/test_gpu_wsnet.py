@@ -1,0 +1,206 @@
+"""GPU parity of the warm-start network kernels (through the C ABI) against
+the FP64 reference in oracle/wsnet.py.
+
+Convolutions: both sides get the same bfloat16-rounded operands; the GPU
+multiplies them exactly and accumulates in FP32, so each output may differ by
+FP32 rounding of the accumulation: |gpu - ref| <= 1e-5 * sum |terms| (the
+reference evaluated on |x| and |w|), far above K * 2^-24 for K <= 2592 terms.
+Whole network: the reference rounds the same operands and stored activations
+to bfloat16 (``rnd``); remaining differences are FP32 arithmetic and the odd
+value that lands on the other side of a bfloat16 rounding boundary.  Such a
+flip is likely for about 1e-7 / 2^-8 of the stored values (FP32 against FP64
+accumulation, against the bfloat16 spacing), i.e. tens per sample, and each
+one moves a stored activation by 2^-8 relative and spreads through the later
+layers.  Measured at 13^3 with 16/32/64 channels the output differs from the
+rounding reference by 0.17% RMS, while bfloat16 operands as such move it by
+0.4% from the exact FP64 network.  So the output is held to 3e-3 RMS (1e-2 at
+its worst element) against the rounding reference and 1e-2 RMS against the
+exact network, and every parameter group's gradient to 1e-2 in relative L2
+norm; a wrong index, sign or operand gives errors of order one."""
+import numpy as np
+import pytest
+
+from oracle import wsnet as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1903_08882_amd import lws as L  # noqa: E402
+from paper_1903_08882_amd import synth  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def bits(a):
+    """bfloat16 bits (int16 CUDA tensor) of the values of a, rounded as W.bf16_round."""
+    f = W.bf16_round(a).astype(np.float32)
+    u = (f.view(np.uint32) >> 16).astype(np.uint16)
+    return torch.from_numpy(u.view(np.int16).reshape(-1).copy()).cuda()
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32).reshape(-1)).cuda()
+
+
+def rand(shape, seed, stream, scale=1.0):
+    n = int(np.prod(shape))
+    return scale * synth.uniform(seed, stream, n).reshape(shape)
+
+
+CASES = [  # (B, D, H, W, cin, cout, shared)
+    (2, 5, 6, 7, 8, 16, False), (1, 3, 4, 5, 8, 8, True), (3, 4, 4, 6, 48, 16, False),
+    (2, 5, 5, 5, 96, 32, False), (1, 6, 5, 4, 64, 64, False), (2, 4, 3, 5, 24, 40, True)]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_conv_forward_matches_reference(case):
+    B, D, H, Wd, ci, co, shared = case
+    say(f"[conv fwd] {case}")
+    X = W.bf16_round(rand((1 if shared else B, D, H, Wd, ci), 11, 0))
+    Wt = W.bf16_round(rand((27, ci, co), 11, 1, 0.2))
+    wg = f32(rand((27, ci, co), 11, 1, 0.2))
+    packed = L.lws_pack_weights(wg, ci, co, 0)
+    z = L.lws_conv3d_forward(bits(X), shared, ci, packed, co, (B, D, H, Wd)).cpu().numpy()
+    Xb = np.broadcast_to(X, (B, D, H, Wd, ci))
+    ref = W.conv3d(Xb, Wt).reshape(-1)
+    bound = 1e-5 * W.conv3d(np.abs(Xb), np.abs(Wt)).reshape(-1) + 1e-30
+    err = np.abs(z - ref)
+    assert np.all(err <= bound), f"worst {np.max(err / bound):.3g}"
+
+
+@pytest.mark.parametrize("case", [(2, 5, 6, 7, 16, 8), (1, 4, 5, 3, 48, 16), (2, 3, 4, 5, 96, 32),
+                                  (1, 5, 5, 5, 16, 8), (2, 4, 4, 4, 128, 64)])
+def test_conv_backward_data_matches_reference(case):
+    B, D, H, Wd, ci, co = case
+    say(f"[conv bwd data] {case}")
+    G = W.bf16_round(rand((B, D, H, Wd, co), 12, 0))
+    wf = rand((27, ci, co), 12, 1, 0.2)
+    Wt = W.bf16_round(wf)
+    packed = L.lws_pack_weights(f32(wf), ci, co, 1)
+    dx = L.lws_conv3d_backward_data(bits(G), co, packed, ci, (B, D, H, Wd)).cpu().numpy()
+    ref = W.conv3d_bwd_data(G, Wt).reshape(-1)
+    bound = 1e-5 * W.conv3d_bwd_data(np.abs(G), np.abs(Wt)).reshape(-1) + 1e-30
+    err = np.abs(dx - ref)
+    assert np.all(err <= bound), f"worst {np.max(err / bound):.3g}"
+
+
+@pytest.mark.parametrize("case", [(2, 5, 6, 7, 8, 16, False), (1, 4, 4, 4, 8, 8, True),
+                                  (3, 17, 17, 17, 16, 16, False), (4, 9, 9, 9, 8, 16, True),
+                                  (2, 5, 5, 5, 96, 32, False), (1, 3, 5, 4, 64, 64, False)])
+def test_conv_backward_weight_matches_reference(case):
+    B, D, H, Wd, ci, co, shared = case
+    say(f"[conv bwd weight] {case}")
+    X = W.bf16_round(rand((1 if shared else B, D, H, Wd, ci), 13, 0))
+    G = W.bf16_round(rand((B, D, H, Wd, co), 13, 1))
+    dw = L.lws_conv3d_backward_weight(bits(X), shared, ci, bits(G), co, (B, D, H, Wd)).cpu().numpy()
+    ref = W.conv3d_bwd_weight(X, G).reshape(-1)
+    bound = 1e-5 * W.conv3d_bwd_weight(np.abs(X), np.abs(G)).reshape(-1) + 1e-30
+    err = np.abs(dw - ref)
+    assert np.all(err <= bound), f"worst {np.max(err / bound):.3g}"
+
+
+def test_conv_argument_checks():
+    x = torch.zeros(64, dtype=torch.int16, device="cuda")
+    p = torch.zeros(L.lws_packed_elems(8, 8), dtype=torch.int16, device="cuda")
+    with pytest.raises(L.LBMError):
+        L.lws_conv3d_forward(x, 0, 4, p, 8, (1, 2, 2, 2))          # cin not a multiple of 8
+    p80 = torch.zeros(L.lws_packed_elems(8, 80), dtype=torch.int16, device="cuda")
+    with pytest.raises(L.LBMError):
+        L.lws_conv3d_forward(x, 0, 8, p80, 80, (1, 1, 1, 1))       # cout above 64
+
+
+def small_net(M, ch, B, seed):
+    names = W.param_shapes(ch)
+    p = {}
+    for k, (name, shp) in enumerate(names):
+        a = synth.uniform(seed, k, int(np.prod(shp))).reshape(shp)
+        p[name] = (np.sqrt(6.0 / (27 * shp[1])) if name.endswith(".W") else 0.2) * a
+    flat32 = W.flatten(p, ch).astype(np.float32)
+    p = W.unflatten(flat32.astype(np.float64), ch)        # the reference sees the FP32 values
+    ra_pr = np.stack([10 ** (4 + 3 * (synth.uniform(seed, 90, B) + 1) / 2),
+                      np.where(synth.uniform(seed, 91, B) > 0, 7.0, 0.71)], axis=-1)
+    target = 0.3 * synth.uniform(seed, 92, B * 4 * M ** 3).reshape(B, 4, M, M, M)
+    return p, flat32, ra_pr, target
+
+
+@pytest.mark.parametrize("M,ch,B", [(9, (16, 16, 16), 2), (13, (16, 32, 64), 3)])
+def test_network_forward_and_gradient_match_reference(M, ch, B):
+    say(f"[net] M={M} ch={ch} B={B}")
+    p, flat, ra_pr, target = small_net(M, ch, B, synth.SEED0 + 200)
+    net = L.lws_net_create(M, B, ch)
+    assert L.lws_net_param_count(net) == flat.size
+    L.lws_net_set_params(net, flat)
+    assert np.array_equal(L.lws_net_get_params(net), flat)
+    out = L.lws_net_forward(net, ra_pr).cpu().numpy().reshape(B, M, M, M, 8)
+    cond = W.condition(ra_pr[:, 0], ra_pr[:, 1])
+    ref, cache = W.forward(p, cond, M, ch, rnd=W.bf16_round)
+    exact, _ = W.forward(p, cond, M, ch)
+    rms = np.sqrt(np.mean((out - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+    worst = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    rms_exact = np.sqrt(np.mean((out - exact) ** 2)) / np.sqrt(np.mean(exact ** 2))
+    scale = np.tile([2.0, 2.0, 2.0, 1.0], (B, 1))
+    loss = L.lws_net_loss_grad(net, ra_pr, f32(target), scale)
+    tgt = np.moveaxis(target, 1, -1) * scale[:, None, None, None, :]
+    ref_loss, dout = W.mse(ref, tgt)
+    g = W.unflatten(L.lws_net_get_grad(net).astype(np.float64), ch)
+    gr = W.backward(p, cache, dout, ch)
+    rel = {name: np.linalg.norm(g[name] - gr[name]) / max(np.linalg.norm(gr[name]), 1e-30)
+           for name, _ in W.param_shapes(ch)}
+    say(f"[net] output rms {rms:.2e} worst {worst:.2e} (exact network: rms {rms_exact:.2e}); "
+        f"loss {loss:.6g} vs {ref_loss:.6g}; "
+        f"worst gradient group {max(rel, key=rel.get)} {max(rel.values()):.2e}")
+    assert rms <= 3e-3 and worst <= 1e-2 and rms_exact <= 1e-2
+    assert abs(loss - ref_loss) <= 2e-3 * ref_loss
+    for name, r in rel.items():
+        assert r <= 1e-2, (name, r)
+
+
+def test_adam_step_matches_reference():
+    M, ch, B = 9, (16, 16, 16), 2
+    p, flat, ra_pr, target = small_net(M, ch, B, synth.SEED0 + 201)
+    net = L.lws_net_create(M, B, ch)
+    L.lws_net_set_params(net, flat)
+    m = np.zeros(flat.size)
+    v = np.zeros(flat.size)
+    x = flat.astype(np.float64)
+    for t in (1, 2, 3):
+        L.lws_net_loss_grad(net, ra_pr, f32(target))
+        g = L.lws_net_get_grad(net).astype(np.float64)
+        x = L.lws_net_get_params(net).astype(np.float64)
+        x, m, v = W.adam(x, g, m, v, t, 1e-3)
+        L.lws_net_adam(net, 1e-3)
+        got = L.lws_net_get_params(net).astype(np.float64)
+        assert np.max(np.abs(got - x)) <= 1e-6 * max(1.0, np.max(np.abs(x))), t
+
+
+def test_training_reduces_the_loss():
+    M, ch, B = 9, (16, 16, 16), 4
+    p, flat, ra_pr, _ = small_net(M, ch, B, synth.SEED0 + 202)
+    # a smooth target that depends on the conditioning
+    c = (np.arange(M) + 0.5) / M
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    cond = W.condition(ra_pr[:, 0], ra_pr[:, 1])
+    target = np.stack([np.stack([np.sin(np.pi * x) * np.sin(np.pi * z) * (0.5 + 0.3 * cb[0]),
+                                 0 * x, np.sin(np.pi * x) * z * (1 - z) * cb[1],
+                                 0.5 - x]) for cb in cond])
+    net = L.lws_net_create(M, B, ch)
+    L.lws_net_set_params(net, flat)
+    t = f32(target)
+    first = L.lws_net_loss_grad(net, ra_pr, t)
+    for _ in range(150):
+        L.lws_net_adam(net, 3e-3)
+        last = L.lws_net_loss_grad(net, ra_pr, t)
+    say(f"[train] loss {first:.4g} -> {last:.4g}")
+    assert last < 0.1 * first
+
+
+@pytest.mark.parametrize("cell,M,N", [(0, 9, 20), (1, 13, 7), (0, 5, 5)])
+def test_upsample_matches_reference(cell, M, N):
+    pred = rand((M, M, M, 8), 14, 0, 0.4)
+    out = L.lws_upsample_fields(f32(pred), M, 8, N, cell, 0.057, 0.5, -0.5).cpu().numpy()
+    ref = W.upsample_fields(pred.astype(np.float32).astype(np.float64), M, N, cell, 0.057, 0.5, -0.5)
+    assert np.max(np.abs(out - ref.reshape(-1))) <= 1e-12

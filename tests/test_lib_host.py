@@ -118,3 +118,19 @@ def test_create_rejects_bad_buffers_without_touching_the_gpu():
                         ctypes.byref(h))
     assert rc == -1
     assert lib.lbm_strerror(-5) == b"non-finite result (diverged)"
+
+
+def test_warm_start_symbols_exported_and_bound():
+    from paper_1903_08882_amd import lws
+    text = open(os.path.join(ROOT, "include", "lws.h")).read()
+    syms = set(re.findall(r"^LBM_API[^(]*?\b(lws_\w+)\(", text, flags=re.M))
+    assert len(syms) >= 15
+    lib = lws.lib()
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert hasattr(lws, s) or s == "lws_last_error", s
+    assert syms == set(lws._SIG)
+    # host-only size queries
+    assert lws.lws_packed_elems(8, 16, 0) == 16 * 224
+    assert lws.lws_packed_elems(48, 16, 1) == 48 * 448
+    assert lws.lws_packed_elems(0, 16, 0) == 0

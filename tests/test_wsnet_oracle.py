@@ -190,3 +190,43 @@ def test_bf16_rounding_ties_to_even():
                      one + 2.0 ** -8 + 2.0 ** -20])
     want = np.array([one, one, one + 2.0 ** -6, one + 2.0 ** -7, -3.0, 0.0, one + 2.0 ** -7])
     assert np.array_equal(W.bf16_round(vals), want)
+
+
+def test_upsample_same_grid_is_identity_in_lattice_units():
+    r = rng(9)
+    M = 5
+    pred = r.standard_normal((M, M, M, 8))
+    out = W.upsample_fields(pred, M, M, 0, U=0.05, T_hot=0.5, T_cold=-0.5)
+    assert np.allclose(out[:3], 0.05 * np.moveaxis(pred[..., :3], -1, 0), rtol=0, atol=1e-15)
+    assert np.allclose(out[3], pred[..., 3], rtol=0, atol=1e-15)
+
+
+def test_upsample_interior_reproduces_trilinear_and_walls_anchor():
+    M, N = 6, 13
+    c = (np.arange(M) + 0.5) / M
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    f = 0.3 + 0.2 * x - 0.1 * y + 0.4 * z + 0.7 * x * y * z
+    pred = np.zeros((M, M, M, 4))
+    pred[..., 0] = f
+    pred[..., 3] = f
+    out = W.upsample_fields(pred, M, N, 0, U=1.0, T_hot=0.5, T_cold=-0.5)
+    q = (np.arange(N) + 0.5) / N
+    inside = (q >= c[0]) & (q <= c[-1])
+    zq, yq, xq = np.meshgrid(q, q, q, indexing="ij")
+    fq = 0.3 + 0.2 * xq - 0.1 * yq + 0.4 * zq + 0.7 * xq * yq * zq
+    m = np.ix_(inside, inside, inside)
+    assert np.allclose(out[0][m], fq[m], rtol=0, atol=1e-13)
+    assert np.allclose(out[3][m], fq[m], rtol=0, atol=1e-13)
+    # the first lattice node of an M = 2 grid sampled at N = 4 sits halfway
+    # between the wall and node 0: u is half the node value, T half the hot
+    # wall's +1/2 plus half the node value along x, the node value along y
+    pred = np.ones((2, 2, 2, 4))
+    out = W.upsample_fields(pred, 2, 4, 0, U=1.0, T_hot=0.5, T_cold=-0.5)
+    assert np.isclose(out[0][1, 1, 0], 0.5)                  # x wall only
+    assert np.isclose(out[0][1, 0, 1], 0.5)                  # y wall only
+    assert np.isclose(out[3][1, 1, 0], 0.5 * 0.5 + 0.5)      # isothermal x wall
+    assert np.isclose(out[3][1, 1, 3], 0.5 * -0.5 + 0.5)     # cold wall
+    assert np.isclose(out[3][1, 0, 1], 1.0)                  # adiabatic y wall
+    # Rayleigh-Benard: z walls isothermal, x adiabatic
+    out = W.upsample_fields(pred, 2, 4, 1, U=1.0, T_hot=0.5, T_cold=-0.5)
+    assert np.isclose(out[3][0, 1, 1], 0.75) and np.isclose(out[3][1, 1, 0], 1.0)
