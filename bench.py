@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--sample-every", type=int, default=100)
     ap.add_argument("--residual-every", type=int, default=1000)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--waves", type=int, nargs=2, default=(0, 0), metavar=("EVEN", "ODD"),
+                    help="occupancy caps of the step kernel (0 = library default, -1 = none)")
     ap.add_argument("--cpu-steps", type=int, default=30,
                     help="oracle steps of the CPU baseline sample (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -96,7 +98,8 @@ def main():
 
     torch.cuda.set_device(0)
     N = a.N
-    opts = B.lbm_default_opts(sample_every=a.sample_every, block=a.block)
+    opts = B.lbm_default_opts(sample_every=a.sample_every, block=a.block, waves_even=a.waves[0],
+                              waves_odd=a.waves[1])
     h = B.lbm_create(N, a.Ra, a.Pr, a.cell, a.storage, opts)
     fields = torch.from_numpy(synth.rest_with_noise(N).reshape(-1)).cuda()
     B.lbm_set_fields(h, fields)

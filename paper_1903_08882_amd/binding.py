@@ -40,7 +40,8 @@ class LBMError(RuntimeError):
 
 class lbm_opts(ctypes.Structure):
     _fields_ = [("U", ctypes.c_double), ("T0", ctypes.c_double),
-                ("sample_every", ctypes.c_int), ("block", ctypes.c_int)]
+                ("sample_every", ctypes.c_int), ("block", ctypes.c_int),
+                ("waves_even", ctypes.c_int), ("waves_odd", ctypes.c_int)]
 
 
 class lbm_params(ctypes.Structure):

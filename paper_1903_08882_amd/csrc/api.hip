@@ -57,6 +57,8 @@ void lbm_default_opts(lbm_opts *o) {
     o->T0 = 0.0;
     o->sample_every = 0;
     o->block = 0;
+    o->waves_even = 0;
+    o->waves_odd = 0;
 }
 
 int lbm_derive_params(int N, double Ra, double Pr, int cell, int storage, const lbm_opts *opts,
@@ -124,6 +126,7 @@ int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opt
     if (opts) o = *opts;
     int block = o.block ? o.block : 256;
     if (block < 64 || block > 256 || block % 64) return LBM_EINVAL;
+    if (o.waves_even < -1 || o.waves_even > 8 || o.waves_odd < -1 || o.waves_odd > 8) return LBM_EINVAL;
     if (dev_buf && (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return LBM_EINVAL;
     lbmk::Layout L = lbmk::make_layout(N, storage);
     if (dev_buf && buf_bytes < L.total) return LBM_ENOMEM;
@@ -135,6 +138,12 @@ int lbm_create(int N, double Ra, double Pr, int cell, int storage, const lbm_opt
     h->L = L;
     h->storage = storage;
     h->block = block;
+    {
+        int w[2];
+        lbmk::default_waves(storage, w);
+        h->waves[0] = o.waves_even == 0 ? w[0] : (o.waves_even < 0 ? 0 : o.waves_even);
+        h->waves[1] = o.waves_odd == 0 ? w[1] : (o.waves_odd < 0 ? 0 : o.waves_odd);
+    }
     h->geo.N = N;
     h->geo.N2 = static_cast<uint32_t>(N) * static_cast<uint32_t>(N);
     h->geo.magic = static_cast<uint32_t>((0x100000000ull + N - 1) / N);
@@ -728,6 +737,8 @@ int lbm_batch_create(int K, const int *N, const double *Ra, const double *Pr, co
         }
         h->in_batch = true;
         h->block = b->block;
+        b->waves[0] = h->waves[0];
+        b->waves[1] = h->waves[1];
         b->cav.push_back(h);
         b->active.push_back(1);
         b->last_res.push_back(INFINITY);

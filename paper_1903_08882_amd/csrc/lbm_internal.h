@@ -80,6 +80,7 @@ struct lbm {
     lbmk::Geo geo{};
     int storage = 0;
     int block = 256;
+    int waves[2] = {0, 0};   // occupancy cap of the step kernel (even, odd); 0 = none
     void *buf = nullptr;     // device buffer (caller's or ours)
     bool own_buf = false;
     int parity = 0;          // 0: planes hold f_i(x) in slot i; 1: post-collision swapped
@@ -100,6 +101,7 @@ struct lbm_batch {
     int K = 0;
     int storage = 0;
     int block = 256;
+    int waves[2] = {0, 0};
     std::vector<lbm_t *> cav;
     std::vector<int> active;
     std::vector<double> last_res;      // last max |dT| of each cavity (inf before any check)
@@ -134,6 +136,11 @@ hipError_t launch_step_batch(const lbm_batch *b, int parity, hipStream_t s);
 // Fields (u, v, w, T) trilinearly resampled onto M^3 nodes, FP32 [4][M^3].
 hipError_t launch_resample(const lbm_t *h, int M, float *out, hipStream_t s);
 constexpr size_t kMaxDescBytes = 256;   // upper bound of sizeof(CavityDesc<double>)
+// Dynamic LDS bytes that cap a block of `block` threads at `waves` waves per
+// SIMD on the current device (0 when waves <= 0).
+uint32_t lds_cap_bytes(int waves, int block);
+// Library default occupancy caps (even, odd) of the step kernel per storage.
+void default_waves(int storage, int out[2]);
 // Centreline maxima of u (over z) and w (over x) into res[kResPeak..+3].
 hipError_t launch_centerline(const lbm_t *h, hipStream_t s);
 

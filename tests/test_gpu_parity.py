@@ -153,6 +153,25 @@ def test_block_sizes_give_identical_results():
             assert np.array_equal(pop, ref), block
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_occupancy_caps_give_identical_results(storage):
+    """The caps only reserve LDS; every setting computes the same populations."""
+    ref = None
+    for w in ((-1, -1), (0, 0), (2, 3), (1, 1), (4, 2)):
+        h = B.lbm_create(23, 1e5, 0.71, 0, storage,
+                         B.lbm_default_opts(U=0.1, waves_even=w[0], waves_odd=w[1]))
+        rho, uvwT = synth.rich_fields(23)
+        B.lbm_set_fields(h, dev(uvwT))
+        B.lbm_step(h, 7)
+        pop = B.lbm_get_populations(h).cpu().numpy()
+        if ref is None:
+            ref = pop
+        else:
+            assert np.array_equal(pop, ref), w
+    with pytest.raises(B.LBMError):
+        B.lbm_create(9, 1e5, 0.71, 0, storage, B.lbm_default_opts(waves_even=9))
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s"])
 def test_set_get_populations_round_trip(storage):
     N = 9

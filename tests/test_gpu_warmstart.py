@@ -1,0 +1,58 @@
+"""What the trained warm-start network gains over a start from rest, end to
+end on the GPU at a size that runs in seconds: twelve 17^3 side-heated
+cavities (Ra log-uniform on [1e4, 1e5], Pr 0.71) are advanced to steady
+state in one batch, their fields resampled to 17^3 train the network, and a
+held-out cavity (Ra 3e4, not in the training set) is run to the same steady-
+state criterion from rest and from the network's prediction."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1903_08882_amd import binding as B  # noqa: E402
+from paper_1903_08882_amd import lws as L  # noqa: E402
+from paper_1903_08882_amd import synth  # noqa: E402
+from paper_1903_08882_amd import warmstart as WS  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def steady_fields(N, M, Ras, Pr, tol):
+    K = len(Ras)
+    b = B.lbm_batch_create([N] * K, Ras, [Pr] * K, [0] * K, "fp32")
+    for k in range(K):
+        f = torch.from_numpy(synth.rest_with_noise(N, synth.SEED0 + 50 + k).reshape(-1)).cuda()
+        B.lbm_set_fields(B.lbm_batch_cavity(b, k), f)
+    steps, res = B.lbm_batch_run_to_steady(b, 500, tol, 200_000)
+    assert all(r < tol for r in res), res
+    fields = torch.empty((K, 4, M, M, M), dtype=torch.float32, device="cuda")
+    for k in range(K):
+        B.lbm_resample_fields(B.lbm_batch_cavity(b, k), M, out=fields[k].view(-1))
+    torch.cuda.synchronize()
+    return fields, max(steps)
+
+
+def test_warm_start_reaches_steady_state_in_fewer_steps():
+    N = M = 17
+    Pr = 0.71
+    Ras = list(10 ** np.linspace(4, 5, 12))
+    fields, sweep_steps = steady_fields(N, M, Ras, Pr, 2e-6)
+    say(f"[warm start] training data: 12 cavities steady after <= {sweep_steps} steps")
+    cav = [{"N": N, "Ra": r, "Pr": Pr} for r in Ras]
+    net, hist = WS.train(fields, cav, iters=400, batch=6, lr=3e-3, holdout=0, ch=(16, 16, 16),
+                         log=lambda s: None)
+    say(f"[warm start] loss {hist[0]['train_loss']:.3e} -> {hist[-1]['train_loss']:.3e}")
+    assert hist[-1]["train_loss"] < 0.05 * hist[0]["train_loss"]
+    r = WS.compare(net, N, 3e4, Pr, storage="fp32", check=500, tol=2e-6, max_steps=200_000, probe=2000,
+                   log=lambda s: None)
+    say(f"[warm start] cold {r['cold']['steps']} steps, warm {r['warm']['steps']} steps, "
+        f"Nu cold {r['cold']['Nu']['Nu_hot']:.5f} warm {r['warm']['Nu']['Nu_hot']:.5f}")
+    assert r["cold"]["converged"] and r["warm"]["converged"]
+    assert r["kept_warm_start"]
+    assert r["warm"]["steps"] <= 0.7 * r["cold"]["steps"]
+    assert abs(r["Nu_rel_diff_warm_vs_cold"]) < 5e-3
