@@ -124,17 +124,23 @@ def _run(h, check, tol, max_steps, probe, log, tag, chunk_checks=10):
         hist += hh
         if at_probe is None and (steps >= probe or r < tol):
             at_probe = (steps, r)
-        nu.append((steps, _nu(h)["Nu_hot"]))
-        log(f"# {tag}: step {steps}  max_dT {r:.3e}  Nu_hot {nu[-1][1]:.4f}  {time.perf_counter() - t0:.1f} s")
+        o = _nu(h)
+        nu.append((steps, o["Nu_hot"], o["Nu_cold"]))
+        log(f"# {tag}: step {steps}  max_dT {r:.3e}  Nu_hot {o['Nu_hot']:.4f}  Nu_cold {o['Nu_cold']:.4f}  "
+            f"{time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     return {"steps": steps, "max_dT": r, "converged": r < tol, "wall_s": time.perf_counter() - t0,
             "probe": at_probe, "history": hist, "nu_track": nu}
 
 
-def steps_to_nu(track, ref, rel=5e-3):
-    """First step after which the tracked Nu stays within rel of ref (None if never)."""
+def steps_to_nu(track, ref, rel=5e-3, wall="hot"):
+    """First step after which the tracked hot-wall Nu (wall="hot") or the mean
+    of the hot- and cold-wall Nu (wall="mean") stays within rel of ref (None
+    if never)."""
     first = None
-    for st, v in track:
+    for row in track:
+        st = row[0]
+        v = row[1] if wall == "hot" or len(row) < 3 else 0.5 * (row[1] + row[2])
         if abs(v - ref) <= rel * abs(ref):
             if first is None:
                 first = st
@@ -177,6 +183,7 @@ def compare(net, N, Ra, Pr, storage="fp16s", check=1000, tol=1e-4, max_steps=2_0
         r["storage"] = st
         if ref_nu:
             r["steps_to_Nu_within_0.5pct_of_ref"] = steps_to_nu(r["nu_track"], ref_nu)
+            r["steps_to_mean_Nu_within_0.5pct_of_ref"] = steps_to_nu(r["nu_track"], ref_nu, wall="mean")
         res[tag] = r
         B.lbm_destroy(h)
         log(json.dumps({"run": tag, **{k: v for k, v in r.items() if k not in ("history",)}}))
