@@ -179,29 +179,43 @@ __device__ __forceinline__ uint32_t slot(const View &v, const Geo &g, int q, int
            (qstart<C>(q) << g.bbits) + static_cast<uint32_t>(r & g.bmask) * qsize<C>(q);
 }
 
+// Plain or streaming (non-temporal) access of one stored value.
+template <bool NT, class T>
+__device__ __forceinline__ T ld_raw(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_raw(T *p, T x) {
+    if constexpr (NT) __builtin_nontemporal_store(x, p);
+    else *p = x;
+}
+
 // Loads and stores of f (moving), g_j for j >= 1 (moving) and g_0 (resting).
-template <class C>
+// NT = true marks them streaming: used where every line a wave touches is read
+// once and written back whole by the same wave (the canonical-storage step).
+template <class C, bool NT = false>
 __device__ __forceinline__ typename C::R ld_f(const View &v, uint32_t off,
                                               const Coef<typename C::R> &c) {
-    return dec<C>(*reinterpret_cast<const typename C::S *>(v.base + off), c.isf);
+    return dec<C>(ld_raw<NT>(reinterpret_cast<const typename C::S *>(v.base + off)), c.isf);
 }
-template <class C>
+template <class C, bool NT = false>
 __device__ __forceinline__ typename C::R ld_g(const View &v, uint32_t off, int j,
                                               const Coef<typename C::R> &c) {
-    if (j < C::GW) return static_cast<typename C::R>(*reinterpret_cast<const typename C::W *>(v.base + off));
-    return dec<C>(*reinterpret_cast<const typename C::S *>(v.base + off), c.isg);
+    if (j < C::GW) return static_cast<typename C::R>(ld_raw<NT>(reinterpret_cast<const typename C::W *>(v.base + off)));
+    return dec<C>(ld_raw<NT>(reinterpret_cast<const typename C::S *>(v.base + off)), c.isg);
 }
-template <class C>
+template <class C, bool NT = false>
 __device__ __forceinline__ void st_f(const View &v, uint32_t off, typename C::R x,
                                      const Coef<typename C::R> &c) {
-    *reinterpret_cast<typename C::S *>(const_cast<char *>(v.base) + off) = enc<C>(x, c.sf);
+    st_raw<NT>(reinterpret_cast<typename C::S *>(const_cast<char *>(v.base) + off), enc<C>(x, c.sf));
 }
-template <class C>
+template <class C, bool NT = false>
 __device__ __forceinline__ void st_g(const View &v, uint32_t off, int j, typename C::R x,
                                      const Coef<typename C::R> &c) {
     char *p = const_cast<char *>(v.base) + off;
-    if (j < C::GW) *reinterpret_cast<typename C::W *>(p) = static_cast<typename C::W>(x);
-    else *reinterpret_cast<typename C::S *>(p) = enc<C>(x, c.sg);
+    if (j < C::GW) st_raw<NT>(reinterpret_cast<typename C::W *>(p), static_cast<typename C::W>(x));
+    else st_raw<NT>(reinterpret_cast<typename C::S *>(p), enc<C>(x, c.sg));
 }
 
 // Component of D3Q7 link j along the isothermal axis (x side-heated, z RB).
@@ -213,7 +227,13 @@ __device__ __forceinline__ constexpr int iso_comp(int j) {
 // ---------------------------------------------------------------------------
 // Gather the pre-collision populations f_i(x, t), g_i(x, t) of a node.
 // SW = false: canonical storage; SW = true: swapped storage (see top).
-// f is returned as deviations f_i - w_i.
+// f is returned as deviations f_i - w_i.  In canonical storage a wave reads
+// and then rewrites exactly the lines of its own nodes, so those accesses are
+// streaming (non-temporal): at 257^3 this took the canonical-storage step from
+// 603 to 535 us and, with less dirty data left behind in the caches, the
+// swapped-storage step after it from 670 to 641 us (FP32).  Streaming hints on
+// the swapped-storage accesses, whose lines are shared with neighbouring
+// waves, made that step slower.
 // ---------------------------------------------------------------------------
 template <class C, int CELL, bool SW>
 __device__ __forceinline__ void gather(const typename C::S *__restrict__ pop, const Geo &g,
@@ -224,7 +244,7 @@ __device__ __forceinline__ void gather(const typename C::S *__restrict__ pop, co
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         if constexpr (!SW) {
-            f[i] = ld_f<C>(v, slot<C>(v, g, i, 0, 0, 0), c);
+            f[i] = ld_f<C, true>(v, slot<C>(v, g, i, 0, 0, 0), c);
         } else {
             const bool out = up_out(EX[i], EY[i], EZ[i], d, g.N);
             const uint32_t off = out ? slot<C>(v, g, i, 0, 0, 0)
@@ -235,7 +255,7 @@ __device__ __forceinline__ void gather(const typename C::S *__restrict__ pop, co
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         if constexpr (!SW) {
-            h[j] = ld_g<C>(v, slot<C>(v, g, kQF + j, 0, 0, 0), j, c);
+            h[j] = ld_g<C, true>(v, slot<C>(v, g, kQF + j, 0, 0, 0), j, c);
         } else {
             const bool out = up_out(GX[j], GY[j], GZ[j], d, g.N);
             const uint32_t off = out ? slot<C>(v, g, kQF + j, 0, 0, 0)
@@ -259,7 +279,7 @@ __device__ __forceinline__ void scatter(typename C::S *__restrict__ pop, const G
 #pragma unroll
     for (int i = 0; i < kQF; ++i) {
         if constexpr (!SW) {
-            st_f<C>(v, slot<C>(v, g, OPP[i], 0, 0, 0), f[i], c);
+            st_f<C, true>(v, slot<C>(v, g, OPP[i], 0, 0, 0), f[i], c);
         } else {
             const bool out = down_out(EX[i], EY[i], EZ[i], d, g.N);
             const uint32_t off = out ? slot<C>(v, g, OPP[i], 0, 0, 0)
@@ -270,7 +290,7 @@ __device__ __forceinline__ void scatter(typename C::S *__restrict__ pop, const G
 #pragma unroll
     for (int j = 0; j < kQG; ++j) {
         if constexpr (!SW) {
-            st_g<C>(v, slot<C>(v, g, kQF + GOPP[j], 0, 0, 0), j, h[j], c);
+            st_g<C, true>(v, slot<C>(v, g, kQF + GOPP[j], 0, 0, 0), j, h[j], c);
         } else {
             const bool out = down_out(GX[j], GY[j], GZ[j], d, g.N);
             const uint32_t off = out ? slot<C>(v, g, kQF + GOPP[j], 0, 0, 0)
@@ -1058,13 +1078,18 @@ uint32_t lds_cap_bytes(int waves, int block) {
 }
 
 void default_waves(int storage, int out[2]) {
-    // measured on the 257^3 step (FP32: 69.3% of 8 TB/s against 67.1% uncapped)
+    // measured on the 257^3 step with streaming canonical-storage accesses:
+    // FP32 587 us capped against 604 uncapped, FP16 380 against 383, FP64
+    // 1207 against 1215
     out[0] = out[1] = 0;
     if (storage == LBM_FP32) {
         out[0] = 2;
         out[1] = 3;
     } else if (storage == LBM_FP16S) {
         out[0] = 3;
+    } else {
+        out[0] = 2;
+        out[1] = 2;
     }
 }
 

@@ -94,9 +94,11 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restric
     f32x4 acc[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // (tap, channel) of this lane's reduction index k = k0 + 8 grp, advanced by
+    // 32 per step without a division
+    int t = (8 * grp) / cin, ci = 8 * grp - t * cin;
     for (int k0 = 0; k0 < kpad; k0 += 32) {
         const int k = k0 + 8 * grp;
-        const int t = k / cin, ci = k - t * cin;
         uint4 av = {0u, 0u, 0u, 0u};
         if (valid && t < 27) {
             const int nz = pz + t / 9 - 1, ny = py + (t / 3) % 3 - 1, nx = px + t % 3 - 1;
@@ -110,6 +112,11 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restric
         for (int j = 0; j < NT; ++j) {
             const uint4 bv = *reinterpret_cast<const uint4 *>(wp + static_cast<uint64_t>(16 * j + r) * kpad + k);
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
+        }
+        ci += 32;
+        while (ci >= cin) {
+            ci -= cin;
+            ++t;
         }
     }
 #pragma unroll
@@ -126,69 +133,116 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restric
 
 // ---------------------------------------------------------------------------
 // Weight gradient: rows m = t cin + ci, columns co, reduction over voxels in
-// chunks (blockIdx.y); partial tiles go to work[chunk][m][co].
+// chunks (blockIdx.y); partial tiles go to work[chunk][m][co].  A wave owns MT
+// row tiles, so each dz fragment feeds MT MFMAs; voxel coordinates advance
+// incrementally (no divisions in the loop).
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int MT>
 __global__ __launch_bounds__(kThreads) void k_conv_wgrad(const uint16_t *__restrict__ x, int x_shared, int cin,
                                                          const uint16_t *__restrict__ dz, int cout,
                                                          float *__restrict__ work, Grid g, uint64_t chunk) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mrows = 27 * cin;
-    const int m0 = (blockIdx.x * 4 + wave) * 16;
+    const int m0 = (blockIdx.x * 4 + wave) * 16 * MT;
     if (m0 >= mrows) return;                          // whole wave
     const int r = lane & 15, grp = lane >> 4;
-    const int m = m0 + r;
-    const bool mvalid = m < mrows;
-    const int t = mvalid ? m / cin : 0, ci = mvalid ? m - t * cin : 0;
-    const int dzo = t / 9 - 1, dyo = (t / 3) % 3 - 1, dxo = t % 3 - 1;
+    int ci[MT], oz[MT], oy[MT], ox[MT];
+    bool mv[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int m = m0 + 16 * t + r;
+        mv[t] = m < mrows;
+        const int tap = mv[t] ? m / cin : 13;
+        ci[t] = mv[t] ? m - tap * cin : 0;
+        oz[t] = tap / 9 - 1;
+        oy[t] = (tap / 3) % 3 - 1;
+        ox[t] = tap % 3 - 1;
+    }
     const uint64_t u0 = static_cast<uint64_t>(blockIdx.y) * chunk;
     const uint64_t u1 = u0 + chunk < g.total ? u0 + chunk : g.total;
-    f32x4 acc[NT];
+    // coordinates of this lane's first voxel, u0 + 8 grp
+    int px, py, pz;
+    uint32_t pb;
+    {
+        const uint64_t ul = u0 + 8 * grp;
+        pb = static_cast<uint32_t>(ul / g.V);
+        const uint32_t v = static_cast<uint32_t>(ul - static_cast<uint64_t>(pb) * g.V);
+        px = static_cast<int>(v % g.W);
+        const uint32_t q = v / g.W;
+        py = static_cast<int>(q % g.H);
+        pz = static_cast<int>(q / g.H);
+    }
+    f32x4 acc[MT][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (uint64_t ub = u0; ub < u1; ub += 32) {
-        u16x8 av;
-        uint64_t us[8];
+        u16x8 av[MT], bv[NT];
+        int xs = px, ys = py, zs = pz;
+        uint32_t bs = pb;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const uint64_t u = ub + 8 * grp + s;
-            us[s] = u;
-            uint16_t val = 0;
-            if (mvalid && u < u1) {
-                const uint64_t b = u / g.V;
-                const uint32_t v = static_cast<uint32_t>(u - b * g.V);
-                const int px = static_cast<int>(v % g.W);
-                const uint32_t q = v / g.W;
-                const int py = static_cast<int>(q % g.H), pz = static_cast<int>(q / g.H);
-                const int nz = pz + dzo, ny = py + dyo, nx = px + dxo;
-                if (nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W) {
-                    const uint64_t xb = x_shared ? 0 : b * g.V;
-                    val = x[(xb + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + ci];
+            const bool valid = u < u1;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int co = 16 * j + r;
+                bv[j][s] = (valid && co < cout) ? dz[u * cout + co] : uint16_t(0);
+            }
+            const uint64_t xb = x_shared ? 0 : static_cast<uint64_t>(bs) * g.V;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const int nz = zs + oz[t], ny = ys + oy[t], nx = xs + ox[t];
+                uint16_t val = 0;
+                if (valid && mv[t] && nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W)
+                    val = x[(xb + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + ci[t]];
+                av[t][s] = val;
+            }
+            if (++xs == g.W) {
+                xs = 0;
+                if (++ys == g.H) {
+                    ys = 0;
+                    if (++zs == g.D) {
+                        zs = 0;
+                        ++bs;
+                    }
                 }
             }
-            av[s] = val;
         }
-        const bf16x8 a = __builtin_bit_cast(bf16x8, av);
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int co = 16 * j + r;
-            u16x8 bv;
+        for (int t = 0; t < MT; ++t)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) bv[s] = (co < cout && us[s] < u1) ? dz[us[s] * cout + co] : uint16_t(0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
+            for (int j = 0; j < NT; ++j)
+                acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[t]),
+                                                                     __builtin_bit_cast(bf16x8, bv[j]), acc[t][j],
+                                                                     0, 0, 0);
+        // the lane's first voxel moves on by 32
+        px += 32;
+        while (px >= g.W) {
+            px -= g.W;
+            if (++py == g.H) {
+                py = 0;
+                if (++pz == g.D) {
+                    pz = 0;
+                    ++pb;
+                }
+            }
         }
     }
     float *out = work + static_cast<uint64_t>(blockIdx.y) * mrows * cout;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = 16 * j + r;
-        if (co >= cout) continue;
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int mo = m0 + 4 * grp + s;
-            if (mo < mrows) out[static_cast<uint64_t>(mo) * cout + co] = acc[j][s];
+        for (int j = 0; j < NT; ++j) {
+            const int co = 16 * j + r;
+            if (co >= cout) continue;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int mo = m0 + 16 * t + 4 * grp + s;
+                if (mo < mrows) out[static_cast<uint64_t>(mo) * cout + co] = acc[t][j][s];
+            }
         }
-    }
 }
 
 __global__ void k_sum_chunks(const float *__restrict__ work, int nchunks, uint64_t n, float *__restrict__ out) {
@@ -315,20 +369,25 @@ __global__ __launch_bounds__(kThreads) void k_film_bwd(const float *__restrict__
     }
 }
 
-// FiLM parameter gradients from the per-block sums (fixed order).
-__global__ void k_film_grads(const double *__restrict__ part, int nbx, int B, int C, const float *__restrict__ cond,
+// Per-sample totals of the per-block sums: sums[b][2C] (fixed order).
+__global__ void k_film_sums(const double *__restrict__ part, int nbx, int C, double *__restrict__ sums) {
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (t >= 2 * C) return;
+    double acc = 0.0;
+    for (int k = 0; k < nbx; ++k) acc += part[(static_cast<uint64_t>(b) * nbx + k) * 2 * C + t];
+    sums[static_cast<uint64_t>(b) * 2 * C + t] = acc;
+}
+
+// FiLM parameter gradients from the per-sample totals (fixed order).
+__global__ void k_film_grads(const double *__restrict__ sums, int B, int C, const float *__restrict__ cond,
                              float *__restrict__ ggw, float *__restrict__ ggb, float *__restrict__ gbw,
                              float *__restrict__ gbb) {
     const int c = threadIdx.x;
     if (c >= C) return;
     double gw0 = 0, gw1 = 0, gb = 0, bw0 = 0, bw1 = 0, bbs = 0;
     for (int b = 0; b < B; ++b) {
-        double dsc = 0.0, dsh = 0.0;
-        for (int k = 0; k < nbx; ++k) {
-            const double *p = part + (static_cast<uint64_t>(b) * nbx + k) * 2 * C;
-            dsc += p[c];
-            dsh += p[C + c];
-        }
+        const double dsc = sums[static_cast<uint64_t>(b) * 2 * C + c];
+        const double dsh = sums[static_cast<uint64_t>(b) * 2 * C + C + c];
         gw0 += dsc * cond[2 * b];
         gw1 += dsc * cond[2 * b + 1];
         gb += dsc;
@@ -473,11 +532,19 @@ __global__ __launch_bounds__(kThreads) void k_mse(const float *__restrict__ out,
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_doubles(const double *__restrict__ part, int n, double scale, double *__restrict__ out) {
-    if (threadIdx.x || blockIdx.x) return;
+// One block: each thread sums a fixed strided subset, then a fixed tree.
+__global__ __launch_bounds__(kThreads) void k_sum_doubles(const double *__restrict__ part, int n, double scale,
+                                                          double *__restrict__ out) {
+    __shared__ double red[kThreads];
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * scale;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // Per-channel sums of a [rows][C] FP32 array: per-block partials, then a fixed-order total.
@@ -611,10 +678,11 @@ hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *
     const uint64_t chunk = wgrad_chunk(g.total);
     const unsigned nchunks = static_cast<unsigned>((g.total + chunk - 1) / chunk);
     const int mrows = 27 * cin;
-    const dim3 grid(static_cast<unsigned>((mrows + 63) / 64), nchunks);
+    constexpr int MT = 2;
+    const dim3 grid(static_cast<unsigned>((mrows + 64 * MT - 1) / (64 * MT)), nchunks);
     switch ((cout + 15) / 16) {
 #define LWS_CASE(K) \
-    case K: k_conv_wgrad<K><<<grid, kThreads, 0, s>>>(x, x_shared, cin, dz, cout, work, g, chunk); break;
+    case K: k_conv_wgrad<K, MT><<<grid, kThreads, 0, s>>>(x, x_shared, cin, dz, cout, work, g, chunk); break;
         LWS_CASE(1) LWS_CASE(2) LWS_CASE(3) LWS_CASE(4)
 #undef LWS_CASE
     default: return hipErrorInvalidValue;
@@ -685,7 +753,7 @@ struct lws_net {
     uint16_t *doutb = nullptr, *dzb = nullptr;
     float *work = nullptr;
     size_t work_bytes = 0;
-    double *part = nullptr, *loss = nullptr;
+    double *part = nullptr, *loss = nullptr, *fsum = nullptr;
     int nbx = 64;
     std::string err;
 };
@@ -754,7 +822,8 @@ hipError_t layer_bwd(lws_net_t *n, int l, const float *da, int dstride, int doff
                                          n->part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_film_grads<<<1, 64, 0, s>>>(n->part, n->nbx, B, y.cout, n->cond, gp(n, y.oGw), gp(n, y.oGb), gp(n, y.oBw),
+    k_film_sums<<<static_cast<unsigned>(B), 128, 0, s>>>(n->part, n->nbx, y.cout, n->fsum);
+    k_film_grads<<<1, 64, 0, s>>>(n->fsum, B, y.cout, n->cond, gp(n, y.oGw), gp(n, y.oGb), gp(n, y.oBw),
                                   gp(n, y.oBb));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = conv_wgrad(x, x_shared, y.cin, n->dzb, y.cout, gp(n, y.oW), g, n->work, s)) != hipSuccess) return e;
@@ -990,7 +1059,8 @@ int lws_net_create(int M, int max_batch, const int ch[3], lws_net_t **out) {
               alloc(n, &n->dA2, B * std::max({V1 * c2, V2 * c3})) &&
               alloc(n, &n->dIn, B * std::max({V1 * c1, V2 * c2})) &&
               alloc(n, &n->dzb, B * std::max({V0 * c1, V1 * c2, V2 * c3, V0 * 8})) &&
-              alloc(n, &n->part, static_cast<size_t>(B) * n->nbx * 2 * 64 + 4096) && alloc(n, &n->loss, 1);
+              alloc(n, &n->part, static_cast<size_t>(B) * n->nbx * 2 * 64 + 4096) && alloc(n, &n->loss, 1) &&
+              alloc(n, &n->fsum, static_cast<size_t>(B) * 2 * 64);
     for (int l = 0; ok && l < NLAYER; ++l) {
         const Layer &y = n->L[l];
         ok = alloc(n, &n->Z[l], B * n->V[y.level] * y.cout);
@@ -1081,7 +1151,7 @@ int lws_net_loss_grad(lws_net_t *net, int B, const double *ra_pr, const float *t
     if (static_cast<size_t>(nb) > static_cast<size_t>(net->maxB) * net->nbx * 2 * 64 + 4096)
         return net_fail(net, LBM_EINVAL, "loss partial buffer too small");
     k_mse<<<nb, kThreads, 0, s>>>(net->Z[OUT], target, net->tscale, g0, net->dout, net->doutb, lpart);
-    k_sum_doubles<<<1, 1, 0, s>>>(lpart, static_cast<int>(nb), 1.0 / static_cast<double>(g0.total * 4), net->loss);
+    k_sum_doubles<<<1, kThreads, 0, s>>>(lpart, static_cast<int>(nb), 1.0 / static_cast<double>(g0.total * 4), net->loss);
     e = hipGetLastError();
     double l = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&l, net->loss, sizeof l, hipMemcpyDeviceToHost, s);
