@@ -492,3 +492,58 @@ def test_streaming_and_wall_rules_with_collision_switched_off(cell):
                         assert abs(out[qo, z, y, x] - (-pop[q, z, y, x] + two_w * Tw)) < 1e-15
                     else:
                         assert out[qo, z, y, x] == pop[q, z, y, x]
+
+
+def _thermal_collision_matrix(p):
+    """The D3Q7 collision of the oracle linearised about rest (u = 0, T = 0):
+    central differences of oracle.collide in each g_j (the buoyancy coupling
+    enters only at second order in T)."""
+    _, _, w = oracle.velocities19()
+    f = np.array(w, dtype=float)
+    d = 1e-6
+    C = np.zeros((7, 7))
+    for j in range(7):
+        e = np.zeros(7)
+        e[j] = d
+        C[:, j] = (oracle.collide(p, f, e)[1] - oracle.collide(p, f, -e)[1]) / (2 * d)
+    return C
+
+
+def _decay_rate(C, k):
+    """Decay rate of the slowest Fourier mode exp(i k.x) of stream + collide."""
+    c = oracle.velocities7()[0].astype(float)
+    ev = np.linalg.eigvals(np.diag(np.exp(-1j * (c @ k))) @ C)
+    return -np.log(np.max(np.abs(ev)))
+
+
+def _k4_coefficient(p, direction):
+    """beta4 in omega(k) = kappa k^2 + beta4 k^4 + O(k^6) (Richardson over two |k|)."""
+    C = _thermal_collision_matrix(p)
+    kh = np.array(direction, float) / np.linalg.norm(direction)
+    b = [(_decay_rate(C, kk * kh) / kk ** 2 - p.kappa) / kk ** 2 for kk in (0.02, 0.04)]
+    return (4 * b[0] - b[1]) / 3
+
+
+def test_thermal_dispersion_is_fourth_order_and_isotropic():
+    """Sec. 2.3: with q_k = 3 - sqrt(3), q_e = q_nu = 4 sqrt(3) - 6 (Eq. magic,
+    Eq. 4th) the fourth-order term of the diffusion dispersion relation of a
+    Fourier mode on the periodic lattice is the same in every direction -- it
+    vanishes -- while the k^2 term is the kappa of the paper.  Breaking
+    Eq. 4th (q_nu) makes it direction dependent; breaking Eq. magic (q_e) keeps
+    it isotropic but nonzero."""
+    import copy
+    p = oracle.derive(33, 1e5, 0.71, oracle.SIDE_HEATED)
+    C = _thermal_collision_matrix(p)
+    for kk in (1e-3, 2e-3):
+        assert abs(_decay_rate(C, np.array([kk, 0.0, 0.0])) / kk ** 2 - p.kappa) < 1e-6 * p.kappa
+    dirs = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 1, 1), (1, 2, 3)]
+    b = [_k4_coefficient(p, d) for d in dirs]
+    assert max(abs(x) for x in b) < 1e-7
+    q = copy.copy(p)
+    q.q_nu = p.q_k                      # violates Eq. 4th
+    b = [_k4_coefficient(q, d) for d in dirs]
+    assert max(b) - min(b) > 1e-4
+    q = copy.copy(p)
+    q.q_e = p.q_k                       # violates Eq. magic
+    b = [_k4_coefficient(q, d) for d in dirs]
+    assert max(b) - min(b) < 1e-7 and min(abs(x) for x in b) > 1e-4
