@@ -220,8 +220,11 @@ def _raw_floor(p):
 
 @pytest.mark.parametrize("cell", [0, 1])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
-def test_fields_and_observables(cell, storage):
-    pr = Pair(19, 1e5, 0.71, cell, storage, U=0.1)
+@pytest.mark.parametrize("N", [19, 18])
+def test_fields_and_observables(cell, storage, N):
+    """Odd and even N: the mid-line observables average the two central rows
+    for even N."""
+    pr = Pair(N, 1e5, 0.71, cell, storage, U=0.1)
     pr.init_rich()
     pr.step(37)
     tol = 1e-11 if storage == "fp64" else 2e-5

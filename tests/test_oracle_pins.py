@@ -547,3 +547,31 @@ def test_thermal_dispersion_is_fourth_order_and_isotropic():
     q.q_e = p.q_k                       # violates Eq. magic
     b = [_k4_coefficient(q, d) for d in dirs]
     assert max(b) - min(b) < 1e-7 and min(abs(x) for x in b) > 1e-4
+
+
+@pytest.mark.parametrize("cell", [oracle.SIDE_HEATED, oracle.RAYLEIGH_BENARD])
+@pytest.mark.parametrize("N", [8, 9])
+def test_midline_flux_weighting_for_odd_and_even_N(cell, N):
+    """The mid-line Nusselt number (Sec. 3, Table 2) is taken on the wall line
+    at y = 1/2: the central node row for odd N, the mean of the two central
+    rows for even N.  From rest with T linear in y (constant along the other
+    axes) the first step's wall link flux is linear in y (the links through a
+    fixed-T wall carry 2 w_T (T_w - T) of an equilibrium node), so its value on
+    the line y = 1/2 equals its mean over the whole wall, and the one-sided
+    wall gradients likewise.  Taking a single row for even N would miss by
+    half a row's slope, here about 5% of the flux.  Side-heated walls are x
+    faces, whose links are orthogonal to the buoyancy force, so the flux is
+    exactly linear (1e-12); the Rayleigh-Benard walls are z faces, whose links
+    see the force-corrected u_z T term, quadratic in y, so there the flux is
+    linear to about 7e-4 and the bound is 3e-3."""
+    o = oracle.Oracle(N, 1e5, 0.71, cell, U=0.05)
+    f = np.zeros((4, N, N, N))
+    y = np.arange(N)
+    f[3] = (0.1 + 0.3 * (y - 2.0) / N)[None, :, None]
+    o.init_fields(f)
+    o.step(1)
+    r = o.observables_raw()
+    assert abs(r[0]) > 1e-3 and abs(r[1]) > 1e-3
+    tol = 1e-12 if cell == oracle.SIDE_HEATED else 3e-3
+    for whole, mid in ((0, 2), (1, 3), (4, 6), (5, 7)):
+        assert abs(r[mid] - r[whole]) <= tol * abs(r[whole]), (whole, r[whole], r[mid])
