@@ -5,7 +5,8 @@
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: rows are
 // voxels (or, for the weight gradient, (tap, channel) pairs), the reduction
 // runs over (tap, input channel) (or over voxels), columns are output
-// channels.  Activations are channels-last, so the 8 consecutive reduction
+// channels.  A wave owns two 16-row tiles, so every B fragment feeds two
+// MFMAs.  Activations are channels-last, so the 8 consecutive reduction
 // indices a lane feeds to one MFMA are 8 adjacent channels of one tap: one
 // 16-byte load.  The FP32 accumulator tile of a 16x16 MFMA sits in lane l as
 // column l % 16, rows 4 (l / 16) + s, s = 0..3; the A and B operands are fed
@@ -70,48 +71,63 @@ inline unsigned blocks_for(uint64_t n, unsigned per = kThreads) {
 // ---------------------------------------------------------------------------
 // Convolution forward (also the data gradient, with mirrored packed weights)
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int MT>
 __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restrict__ x, int x_shared, int cin,
                                                        const uint16_t *__restrict__ wp, int kpad, int cout,
                                                        float *__restrict__ z, Grid g) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t tile = (static_cast<uint64_t>(blockIdx.x) * 4 + wave) * 16;
-    if (tile >= g.total) return;                      // whole wave
+    const uint64_t tile0 = (static_cast<uint64_t>(blockIdx.x) * 4 + wave) * 16 * MT;
+    if (tile0 >= g.total) return;                     // whole wave
     const int r = lane & 15, grp = lane >> 4;
-    const uint64_t u = tile + r;
-    const bool valid = u < g.total;
-    uint64_t xbase = 0;
-    int px = 0, py = 0, pz = 0;
-    if (valid) {
-        const uint64_t b = u / g.V;
-        const uint32_t v = static_cast<uint32_t>(u - b * g.V);
-        px = static_cast<int>(v % g.W);
-        const uint32_t q = v / g.W;
-        py = static_cast<int>(q % g.H);
-        pz = static_cast<int>(q / g.H);
-        xbase = x_shared ? 0 : b * g.V;
-    }
-    f32x4 acc[NT];
+    bool valid[MT];
+    uint64_t xbase[MT];
+    int px[MT], py[MT], pz[MT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // (tap, channel) of this lane's reduction index k = k0 + 8 grp, advanced by
-    // 32 per step without a division
+    for (int m = 0; m < MT; ++m) {
+        const uint64_t u = tile0 + 16 * m + r;
+        valid[m] = u < g.total;
+        xbase[m] = 0;
+        px[m] = py[m] = pz[m] = 0;
+        if (valid[m]) {
+            const uint64_t b = u / g.V;
+            const uint32_t v = static_cast<uint32_t>(u - b * g.V);
+            px[m] = static_cast<int>(v % g.W);
+            const uint32_t q = v / g.W;
+            py[m] = static_cast<int>(q % g.H);
+            pz[m] = static_cast<int>(q / g.H);
+            xbase[m] = x_shared ? 0 : b * g.V;
+        }
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     int t = (8 * grp) / cin, ci = 8 * grp - t * cin;
+#pragma unroll 2
     for (int k0 = 0; k0 < kpad; k0 += 32) {
         const int k = k0 + 8 * grp;
-        uint4 av = {0u, 0u, 0u, 0u};
-        if (valid && t < 27) {
-            const int nz = pz + t / 9 - 1, ny = py + (t / 3) % 3 - 1, nx = px + t % 3 - 1;
-            if (nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W) {
-                const uint64_t idx = (xbase + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + ci;
-                av = *reinterpret_cast<const uint4 *>(x + idx);
+        bf16x8 a[MT];
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            uint4 av = {0u, 0u, 0u, 0u};
+            if (valid[m] && t < 27) {
+                const int nz = pz[m] + dz, ny = py[m] + dy, nx = px[m] + dx;
+                if (nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W) {
+                    const uint64_t idx = (xbase[m] + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + ci;
+                    av = *reinterpret_cast<const uint4 *>(x + idx);
+                }
             }
+            a[m] = __builtin_bit_cast(bf16x8, av);
         }
-        const bf16x8 a = __builtin_bit_cast(bf16x8, av);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             const uint4 bv = *reinterpret_cast<const uint4 *>(wp + static_cast<uint64_t>(16 * j + r) * kpad + k);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
+            const bf16x8 b = __builtin_bit_cast(bf16x8, bv);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][j], 0, 0, 0);
         }
         ci += 32;
         while (ci >= cin) {
@@ -120,15 +136,17 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restric
         }
     }
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = 16 * j + r;
-        if (co >= cout) continue;
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint64_t uo = tile + 4 * grp + s;
-            if (uo < g.total) z[uo * cout + co] = acc[j][s];
+        for (int j = 0; j < NT; ++j) {
+            const int co = 16 * j + r;
+            if (co >= cout) continue;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const uint64_t uo = tile0 + 16 * m + 4 * grp + s;
+                if (uo < g.total) z[uo * cout + co] = acc[m][j][s];
+            }
         }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -661,11 +679,12 @@ __global__ void k_upsample(const float *__restrict__ pred, int M, int ld, int N,
 // ---------------------------------------------------------------------------
 hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp, int kpad, int cout, float *z,
                     const Grid &g, hipStream_t s) {
-    const unsigned nb = static_cast<unsigned>((g.total + 63) / 64);
+    constexpr int MT = 2;
+    const unsigned nb = static_cast<unsigned>((g.total + 64 * MT - 1) / (64 * MT));
     const int nt = (cout + 15) / 16;
     switch (nt) {
 #define LWS_CASE(K) \
-    case K: k_conv_fwd<K><<<nb, kThreads, 0, s>>>(x, x_shared, cin, wp, kpad, cout, z, g); break;
+    case K: k_conv_fwd<K, MT><<<nb, kThreads, 0, s>>>(x, x_shared, cin, wp, kpad, cout, z, g); break;
         LWS_CASE(1) LWS_CASE(2) LWS_CASE(3) LWS_CASE(4) LWS_CASE(5) LWS_CASE(6) LWS_CASE(7) LWS_CASE(8)
 #undef LWS_CASE
     default: return hipErrorInvalidValue;
