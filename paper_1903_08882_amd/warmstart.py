@@ -133,6 +133,19 @@ def _run(h, check, tol, max_steps, probe, log, tag, chunk_checks=10):
             "probe": at_probe, "history": hist, "nu_track": nu}
 
 
+def keep_warm_start(warm_probe, cold_probe):
+    """The fallback rule: keep the warm start only if, at the probe step, its
+    steady-state residual (max |dT| over one check interval) is below the cold
+    start's.  Probes are (step, residual) or None; a residual that is not a
+    number (a diverged run) never wins."""
+    if warm_probe is None or cold_probe is None:
+        return False
+    w, c = warm_probe[1], cold_probe[1]
+    if not (w == w) or w == float("inf"):
+        return False
+    return not (c == c) or w < c
+
+
 def steps_to_nu(track, ref, rel=5e-3, wall="hot"):
     """First step after which the tracked hot-wall Nu (wall="hot") or the mean
     of the hot- and cold-wall Nu (wall="mean") stays within rel of ref (None
@@ -195,7 +208,7 @@ def compare(net, N, Ra, Pr, storage="fp16s", check=1000, tol=1e-4, max_steps=2_0
     # fall back: the warm start is kept only if its residual at the probe beats
     # that of the cold start in the same storage
     base = res.get("cold_same", cold)
-    keep = (warm["probe"] is not None and base["probe"] is not None and warm["probe"][1] < base["probe"][1])
+    keep = keep_warm_start(warm["probe"], base["probe"])
     chosen = warm if keep else base
     out.update({"cold": {k: v for k, v in cold.items() if k != "history"},
                 "warm": {k: v for k, v in warm.items() if k != "history"},

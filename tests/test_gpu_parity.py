@@ -589,3 +589,28 @@ def test_checkpoint_restart_continues_bit_for_bit(storage, tmp_path):
     B.lbm_step(b, 3)
     assert np.array_equal(B.lbm_get_populations(a).cpu().numpy(),
                           B.lbm_get_populations(b).cpu().numpy())
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_small_configuration_2000_steps_observable_series(storage):
+    """The small configuration (33^3 side-heated, Ra 1e4, Pr 0.71, U = 0.1, rest
+    + seeded noise) for 2000 steps: the population parity of the oracle at step
+    200, and the nondimensional observables every 200 steps (Nu of both walls,
+    Re, the dissipation rates) against the oracle's.  The flow grows from the
+    1e-3 noise to Re ~ 10 over these steps, so the series checks the coupled
+    dynamics, not only a single state.  Tolerances: FP32 accumulates rounding
+    over the run (relative 2e-4 of each number's own scale), FP64 1e-9."""
+    pr = Pair(33, 1e4, 0.71, 0, storage, U=0.1)
+    pr.init_rest_noise()
+    tol = 2e-4 if storage == "fp32" else 1e-9
+    for k in range(10):
+        pr.step(200)
+        if k == 0:
+            pr.check_pop("step 200")
+        ng = B.lbm_nondimensional(B.lbm_get_params(pr.h), B.lbm_observables_raw(pr.h))
+        no = oracle.nondimensional(pr.p, pr.o.observables_raw())
+        say(f"[c0 {storage}] step {200 * (k + 1)}: Nu {ng['Nu_hot']:.6f}/{no['Nu_hot']:.6f} "
+            f"Re {ng['Re_rms']:.5f}/{no['Re_rms']:.5f}")
+        for key, scale in (("Nu_hot", 1.0), ("Nu_cold", 1.0), ("Nu_hot_mid", 1.0), ("Re_rms", no["Re_rms"]),
+                           ("eps_u", no["eps_u"]), ("eps_T", no["eps_T"]), ("Nu_vol", 1.0)):
+            assert abs(ng[key] - no[key]) <= tol * max(abs(no[key]), scale), (k, key, ng[key], no[key])
