@@ -84,9 +84,14 @@ LBM_API int lws_conv3d_backward_weight(const uint16_t *x, int x_shared, int cin,
  * FP64 [4][N^3] for lbm_set_fields.  Beyond the outermost grid nodes each axis
  * is anchored at its walls: velocity 0 on every wall, T_hot / T_cold on the
  * isothermal walls (x for side-heated, z for Rayleigh-Benard), the nearest
- * node's T along adiabatic axes. */
+ * node's T along adiabatic axes.  With symmetrize != 0 (side-heated cell
+ * only; ignored otherwise) each node gets the mean of this interpolation over
+ * the steady cell's symmetries: the half-turn about the y axis through the
+ * centre with T* -> -T* ((x, z) -> (1 - x, 1 - z), (u, w) -> (-u, -w)) and
+ * the mirror y -> 1 - y (v -> -v); errors odd under them are removed. */
 LBM_API int lws_upsample_fields(const float *pred, int M, int ld, int N, int cell, double U,
-                                double T_hot, double T_cold, double *uvwT, void *stream);
+                                double T_hot, double T_cold, int symmetrize, double *uvwT,
+                                void *stream);
 
 /* ---- the network ------------------------------------------------------- */
 

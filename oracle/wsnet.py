@@ -298,14 +298,17 @@ def bf16_round(a):
     return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
 
 
-def upsample_fields(pred, M, N, cell, U, T_hot, T_cold):
+def upsample_fields(pred, M, N, cell, U, T_hot, T_cold, symmetrize=False):
     """Fields on the node-centred M^3 grid (pred [M, M, M, >=4]: u/U, v/U, w/U,
     T*) trilinearly interpolated at the N^3 lattice nodes (i + 1/2)/N, in
     lattice units, [4, N, N, N].  Per axis the samples are the M nodes and,
     half a spacing beyond the outermost ones, the walls: velocity 0 on every
     wall; T* = +1/2 at the low and -1/2 at the high isothermal wall (axis x
     for side-heated, cell 0; z for Rayleigh-Benard), the nearest node's T*
-    across an adiabatic wall."""
+    across an adiabatic wall.  With symmetrize (side-heated only) the result
+    is averaged over the cell's symmetries: the half-turn about the y axis
+    through the centre, (x, z) -> (1 - x, 1 - z) with (u, w, T*) -> -(u, w, T*),
+    and the mirror y -> 1 - y with v -> -v."""
     ext = np.zeros((M + 2,) * 3 + (4,))
     ext[1:-1, 1:-1, 1:-1] = pred[..., :4]
     # temperature beyond adiabatic walls: the nearest node (edges and corners too)
@@ -332,6 +335,11 @@ def upsample_fields(pred, M, N, cell, U, T_hot, T_cold):
                 vals = ext[np.ix_(idx + cz, idx + cy, idx + cx)]          # [N, N, N, 4]
                 wt = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
                 out += np.moveaxis(vals, -1, 0) * wt[None]
+    if symmetrize and cell == 0:
+        turn = np.array([-1.0, 1.0, -1.0, -1.0])[:, None, None, None] * out[:, ::-1, :, ::-1]
+        mirror = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None, None] * out[:, :, ::-1, :]
+        both = np.array([-1.0, -1.0, -1.0, -1.0])[:, None, None, None] * out[:, ::-1, ::-1, ::-1]
+        out = 0.25 * (out + turn + mirror + both)
     Tm, dT = 0.5 * (T_hot + T_cold), T_hot - T_cold
     out[:3] *= U
     out[3] = Tm + dT * out[3]

@@ -625,19 +625,16 @@ __device__ __forceinline__ void axis_samples(double p, int M, int *i0, int *i1, 
     }
 }
 
-__global__ void k_upsample(const float *__restrict__ pred, int M, int ld, int N, int iso_axis, double U,
-                           double T_hot, double T_cold, double *__restrict__ out) {
-    const uint64_t V = static_cast<uint64_t>(N) * N * N;
-    const uint64_t n = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (n >= V) return;
-    const int ix = static_cast<int>(n % N), iy = static_cast<int>((n / N) % N),
-              iz = static_cast<int>(n / (static_cast<uint64_t>(N) * N));
+// Anchored trilinear interpolation of the prediction (u/U, v/U, w/U, T*) at
+// lattice node (ix, iy, iz) of N^3.
+__device__ void interp_at(const float *__restrict__ pred, int M, int ld, int N, int iso_axis, int ix, int iy,
+                          int iz, double acc[4]) {
     int a0[3], a1[3];
     double w[3];
     axis_samples((ix + 0.5) / N, M, &a0[0], &a1[0], &w[0]);
     axis_samples((iy + 0.5) / N, M, &a0[1], &a1[1], &w[1]);
     axis_samples((iz + 0.5) / N, M, &a0[2], &a1[2], &w[2]);
-    double acc[4] = {0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) acc[c] = 0.0;
     for (int corner = 0; corner < 8; ++corner) {
         int idx[3];
         double wt = 1.0;
@@ -666,6 +663,43 @@ __global__ void k_upsample(const float *__restrict__ pred, int M, int ld, int N,
             T = pred[((static_cast<uint64_t>(cl[2]) * M + cl[1]) * M + cl[0]) * ld + 3];
         }
         acc[3] += wt * T;
+    }
+}
+
+// With sym (side-heated cell only), the average over the cell's symmetry
+// group: the half-turn about the y axis through the centre with T* -> -T*
+// ((x, z) -> (1 - x, 1 - z), (u, w) -> (-u, -w)) and the mirror y -> 1 - y
+// (v -> -v).  Lattice nodes map onto lattice nodes.
+__global__ void k_upsample(const float *__restrict__ pred, int M, int ld, int N, int iso_axis, int sym, double U,
+                           double T_hot, double T_cold, double *__restrict__ out) {
+    const uint64_t V = static_cast<uint64_t>(N) * N * N;
+    const uint64_t n = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n >= V) return;
+    const int ix = static_cast<int>(n % N), iy = static_cast<int>((n / N) % N),
+              iz = static_cast<int>(n / (static_cast<uint64_t>(N) * N));
+    double acc[4];
+    interp_at(pred, M, ld, N, iso_axis, ix, iy, iz, acc);
+    if (sym) {
+        double t[4];
+        // half-turn about y: (u, v, w, T) -> (-u, v, -w, -T) at (N-1-ix, iy, N-1-iz)
+        interp_at(pred, M, ld, N, iso_axis, N - 1 - ix, iy, N - 1 - iz, t);
+        acc[0] -= t[0];
+        acc[1] += t[1];
+        acc[2] -= t[2];
+        acc[3] -= t[3];
+        // mirror in y: (u, v, w, T) -> (u, -v, w, T) at (ix, N-1-iy, iz)
+        interp_at(pred, M, ld, N, iso_axis, ix, N - 1 - iy, iz, t);
+        acc[0] += t[0];
+        acc[1] -= t[1];
+        acc[2] += t[2];
+        acc[3] += t[3];
+        // both
+        interp_at(pred, M, ld, N, iso_axis, N - 1 - ix, N - 1 - iy, N - 1 - iz, t);
+        acc[0] -= t[0];
+        acc[1] -= t[1];
+        acc[2] -= t[2];
+        acc[3] -= t[3];
+        for (int c = 0; c < 4; ++c) acc[c] *= 0.25;
     }
     const double Tm = 0.5 * (T_hot + T_cold), dT = T_hot - T_cold;
     out[n] = U * acc[0];
@@ -1001,13 +1035,14 @@ int lws_conv3d_backward_weight(const uint16_t *x, int x_shared, int cin, const u
 }
 
 int lws_upsample_fields(const float *pred, int M, int ld, int N, int cell, double U, double T_hot, double T_cold,
-                        double *uvwT, void *stream) {
+                        int symmetrize, double *uvwT, void *stream) {
     if (!pred || !uvwT || M < 2 || ld < 4 || N < 1 || (cell != LBM_SIDE_HEATED && cell != LBM_RAYLEIGH_BENARD) ||
         !std::isfinite(U) || !std::isfinite(T_hot) || !std::isfinite(T_cold))
         return LBM_EINVAL;
     const uint64_t V = static_cast<uint64_t>(N) * N * N;
     k_upsample<<<blocks_for(V), kThreads, 0, static_cast<hipStream_t>(stream)>>>(
-        pred, M, ld, N, cell == LBM_SIDE_HEATED ? 0 : 2, U, T_hot, T_cold, uvwT);
+        pred, M, ld, N, cell == LBM_SIDE_HEATED ? 0 : 2, (symmetrize && cell == LBM_SIDE_HEATED) ? 1 : 0, U, T_hot,
+        T_cold, uvwT);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 

@@ -28,7 +28,8 @@ _SIG = {
     "lws_conv3d_backward_weight": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P,
                                                   lws_grid, _P, ctypes.c_size_t, _P]),
     "lws_upsample_fields": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P]),
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           _P, _P]),
     "lws_net_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(_P)]),
     "lws_net_destroy": (ctypes.c_int, [_P]),
@@ -128,11 +129,12 @@ def lws_conv3d_backward_weight(x, x_shared, cin, dz, cout, grid, out=None, work=
     return out
 
 
-def lws_upsample_fields(pred, M, ld, N, cell, U, T_hot, T_cold, out=None, stream=None):
+def lws_upsample_fields(pred, M, ld, N, cell, U, T_hot, T_cold, out=None, stream=None, symmetrize=False):
     cellv = {"side_heated": 0, "rayleigh_benard": 1}.get(cell, cell)
     out = out if out is not None else torch.empty(4 * N ** 3, dtype=torch.float64, device=pred.device)
     _check(lib().lws_upsample_fields(_ptr(pred, torch.float32, M ** 3 * ld), int(M), int(ld), int(N), int(cellv),
-                                     float(U), float(T_hot), float(T_cold), _ptr(out, torch.float64, 4 * N ** 3),
+                                     float(U), float(T_hot), float(T_cold), int(bool(symmetrize)),
+                                     _ptr(out, torch.float64, 4 * N ** 3),
                                      _stream(stream)))
     return out
 

@@ -102,11 +102,12 @@ def train(fields, cavities, iters=1500, batch=8, lr=2e-3, holdout=8, seed=synth.
     return net, hist
 
 
-def predict_fields(net, N, Ra, Pr, cell="side_heated", opts=None):
-    """The network's fields for (Ra, Pr), interpolated onto the N^3 lattice (FP64 [4 N^3])."""
+def predict_fields(net, N, Ra, Pr, cell="side_heated", opts=None, symmetrize=False):
+    """The network's fields for (Ra, Pr), interpolated onto the N^3 lattice (FP64
+    [4 N^3]); with symmetrize, averaged over the steady cell's symmetries."""
     p = B.lbm_derive_params(N, Ra, Pr, cell, "fp32", opts)
     pred = L.lws_net_forward(net, [[Ra, Pr]])
-    return L.lws_upsample_fields(pred, net.M, 8, N, cell, p.U, p.T_hot, p.T_cold)
+    return L.lws_upsample_fields(pred, net.M, 8, N, cell, p.U, p.T_hot, p.T_cold, symmetrize=symmetrize)
 
 
 def _run(h, check, tol, max_steps, probe, log, tag, chunk_checks=10):
@@ -168,13 +169,13 @@ def _nu(h):
 
 
 def compare(net, N, Ra, Pr, storage="fp16s", check=1000, tol=1e-4, max_steps=2_000_000, probe=20_000,
-            seed=synth.SEED0 + 1, ref_nu=None, cold_storage=None, runs=None, log=print):
+            seed=synth.SEED0 + 1, ref_nu=None, cold_storage=None, runs=None, symmetrize=False, log=print):
     """Cold start in cold_storage (default: storage) against the warm start in
     storage; with a cold_storage other than storage, a cold start in storage
     is run as well ("cold_same") to separate the two effects."""
     cold_storage = cold_storage or storage
     out = {"N": N, "Ra": Ra, "Pr": Pr, "storage": storage, "cold_storage": cold_storage, "check": check,
-           "tol": tol, "probe": probe}
+           "tol": tol, "probe": probe, "symmetrize": symmetrize}
     res = {}
     plan = [("cold", cold_storage), ("warm", storage)]
     if cold_storage != storage:
@@ -186,7 +187,7 @@ def compare(net, N, Ra, Pr, storage="fp16s", check=1000, tol=1e-4, max_steps=2_0
         if tag != "warm":
             B.lbm_set_fields(h, torch.from_numpy(synth.rest_with_noise(N, seed).reshape(-1)).cuda())
         else:
-            B.lbm_set_fields(h, predict_fields(net, N, Ra, Pr))
+            B.lbm_set_fields(h, predict_fields(net, N, Ra, Pr, symmetrize=symmetrize))
             # one step so the wall flux is defined, then the prediction's own Nu
             B.lbm_step(h, 1)
             out["predicted_Nu"] = _nu(h)
@@ -250,6 +251,8 @@ def main():
     c.add_argument("--max-steps", type=int, default=2_000_000)
     c.add_argument("--ref-nu", type=float, default=None)
     c.add_argument("--runs", default="", help="comma list of cold,warm,cold_same (default all)")
+    c.add_argument("--symmetrize", action="store_true",
+                   help="average the prediction over the side-heated cell's symmetries")
     a = ap.parse_args()
     say = lambda s: print(s, flush=True)  # noqa: E731
     if a.cmd == "train":
@@ -270,7 +273,7 @@ def main():
         L.lws_net_set_params(net, d["params"])
         r = compare(net, a.N, a.Ra, a.Pr, a.storage, a.check, a.tol, a.max_steps, a.probe,
                     ref_nu=a.ref_nu, cold_storage=a.cold_storage,
-                    runs=[x for x in a.runs.split(",") if x] or None, log=say)
+                    runs=[x for x in a.runs.split(",") if x] or None, symmetrize=a.symmetrize, log=say)
         print(json.dumps(r), flush=True)
 
 

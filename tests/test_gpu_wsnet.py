@@ -198,9 +198,11 @@ def test_training_reduces_the_loss():
     assert last < 0.1 * first
 
 
-@pytest.mark.parametrize("cell,M,N", [(0, 9, 20), (1, 13, 7), (0, 5, 5)])
-def test_upsample_matches_reference(cell, M, N):
+@pytest.mark.parametrize("sym", [False, True])
+@pytest.mark.parametrize("cell,M,N", [(0, 9, 20), (1, 13, 7), (0, 5, 5), (0, 6, 9)])
+def test_upsample_matches_reference(cell, M, N, sym):
     pred = rand((M, M, M, 8), 14, 0, 0.4)
-    out = L.lws_upsample_fields(f32(pred), M, 8, N, cell, 0.057, 0.5, -0.5).cpu().numpy()
-    ref = W.upsample_fields(pred.astype(np.float32).astype(np.float64), M, N, cell, 0.057, 0.5, -0.5)
+    out = L.lws_upsample_fields(f32(pred), M, 8, N, cell, 0.057, 0.5, -0.5, symmetrize=sym).cpu().numpy()
+    ref = W.upsample_fields(pred.astype(np.float32).astype(np.float64), M, N, cell, 0.057, 0.5, -0.5,
+                            symmetrize=sym)
     assert np.max(np.abs(out - ref.reshape(-1))) <= 1e-12

@@ -230,3 +230,22 @@ def test_upsample_interior_reproduces_trilinear_and_walls_anchor():
     # Rayleigh-Benard: z walls isothermal, x adiabatic
     out = W.upsample_fields(pred, 2, 4, 1, U=1.0, T_hot=0.5, T_cold=-0.5)
     assert np.isclose(out[3][0, 1, 1], 0.75) and np.isclose(out[3][1, 1, 0], 1.0)
+
+
+def test_upsample_symmetrized_is_invariant_and_keeps_symmetric_fields():
+    r = rng(10)
+    M, N = 6, 11
+    pred = r.standard_normal((M, M, M, 4))
+    out = W.upsample_fields(pred, M, N, 0, U=1.0, T_hot=0.5, T_cold=-0.5, symmetrize=True)
+    # invariant under the half-turn about y (T* odd) and the y mirror (v odd)
+    turn = np.array([-1.0, 1.0, -1.0, -1.0])[:, None, None, None] * out[:, ::-1, :, ::-1]
+    mirror = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None, None] * out[:, :, ::-1, :]
+    assert np.allclose(turn, out, rtol=0, atol=1e-14) and np.allclose(mirror, out, rtol=0, atol=1e-14)
+    assert abs(out[3].mean()) < 1e-14                       # the mean temperature is removed
+    # a prediction that already has the symmetries is left as it was
+    p = pred.copy()
+    p = 0.5 * (p + np.array([-1.0, 1.0, -1.0, -1.0]) * p[::-1, :, ::-1])
+    p = 0.5 * (p + np.array([1.0, -1.0, 1.0, 1.0]) * p[:, ::-1, :])
+    a = W.upsample_fields(p, M, N, 0, U=1.0, T_hot=0.5, T_cold=-0.5, symmetrize=True)
+    b = W.upsample_fields(p, M, N, 0, U=1.0, T_hot=0.5, T_cold=-0.5)
+    assert np.allclose(a, b, rtol=0, atol=1e-14)
