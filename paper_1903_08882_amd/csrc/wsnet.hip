@@ -263,6 +263,109 @@ __global__ __launch_bounds__(kThreads) void k_conv_wgrad(const uint16_t *__restr
         }
 }
 
+// Weight gradient with LDS staging (cin a multiple of 8).  A block owns
+// kWgRows rows (4 waves x 2 tiles of 16) and one voxel chunk.  For each group
+// of 32 voxels it stages, transposed so that 8 consecutive voxels of one
+// channel are 16 contiguous bytes, the dz tile as [co][32] and, for every tap
+// its rows touch, the shifted input x[v + off_t] as [tap][cin][32] (zero where
+// the neighbour leaves the grid); every MFMA operand is then one 16-byte LDS
+// read, and the global traffic is coalesced 16-byte loads.
+constexpr int kWgRows = 128;
+
+int wg_taps(int cin) { return std::min(27, (kWgRows + cin - 1) / cin + 1); }
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_conv_wgrad_lds(const uint16_t *__restrict__ x, int x_shared, int cin,
+                                                             const uint16_t *__restrict__ dz, int cout,
+                                                             float *__restrict__ work, Grid g, uint64_t chunk) {
+    extern __shared__ uint4 lds_raw[];
+    uint16_t *ldz = reinterpret_cast<uint16_t *>(lds_raw);   // [16 NT][32]
+    uint16_t *lx = ldz + 16 * NT * 32;                       // [taps][cin][32]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mrows = 27 * cin;
+    const int m0 = blockIdx.x * kWgRows;
+    const int t_lo = m0 / cin;
+    const int t_hi = min(26, (min(m0 + kWgRows, mrows) - 1) / cin);
+    const int ntap = t_hi - t_lo + 1;
+    const int cgroups = cin / 8;
+    const int r = lane & 15, grp = lane >> 4;
+    bool mv[2];
+    int lrow[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int m = m0 + (wave * 2 + q) * 16 + r;
+        mv[q] = m < mrows;
+        const int t = mv[q] ? m / cin : t_lo;
+        lrow[q] = (t - t_lo) * cin + (mv[q] ? m - t * cin : 0);
+    }
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[q][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint64_t u0 = static_cast<uint64_t>(blockIdx.y) * chunk;
+    const uint64_t u1 = u0 + chunk < g.total ? u0 + chunk : g.total;
+    for (uint64_t ub = u0; ub < u1; ub += 32) {
+        __syncthreads();                                  // the previous group's reads are done
+        for (int e = threadIdx.x; e < 32 * 16 * NT; e += kThreads) {
+            const int co = e % (16 * NT), vi = e / (16 * NT);
+            const uint64_t u = ub + vi;
+            ldz[co * 32 + vi] = (u < u1 && co < cout) ? dz[u * cout + co] : uint16_t(0);
+        }
+        for (int e = threadIdx.x; e < ntap * cgroups * 32; e += kThreads) {
+            const int vi = e & 31, rest = e >> 5;
+            const int cg = rest % cgroups, tt = rest / cgroups;
+            const int t = t_lo + tt;
+            const uint64_t u = ub + vi;
+            uint4 val = {0u, 0u, 0u, 0u};
+            if (u < u1) {
+                const uint64_t b = u / g.V;
+                const uint32_t v = static_cast<uint32_t>(u - b * g.V);
+                const int px = static_cast<int>(v % g.W);
+                const uint32_t qv = v / g.W;
+                const int py = static_cast<int>(qv % g.H), pz = static_cast<int>(qv / g.H);
+                const int nz = pz + t / 9 - 1, ny = py + (t / 3) % 3 - 1, nx = px + t % 3 - 1;
+                if (nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W) {
+                    const uint64_t xb = x_shared ? 0 : b * g.V;
+                    val = *reinterpret_cast<const uint4 *>(
+                        x + (xb + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + 8 * cg);
+                }
+            }
+            const u16x8 h = __builtin_bit_cast(u16x8, val);
+            uint16_t *dst = lx + (tt * cin + 8 * cg) * 32 + vi;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) dst[c * 32] = h[c];
+        }
+        __syncthreads();
+        bf16x8 bfr[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+            bfr[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ldz + (16 * j + r) * 32 + 8 * grp));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            uint4 av = {0u, 0u, 0u, 0u};
+            if (mv[q]) av = *reinterpret_cast<const uint4 *>(lx + lrow[q] * 32 + 8 * grp);
+            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[q][j], 0, 0, 0);
+        }
+    }
+    float *out = work + static_cast<uint64_t>(blockIdx.y) * mrows * cout;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = 16 * j + r;
+            if (co >= cout) continue;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int mo = m0 + (wave * 2 + q) * 16 + 4 * grp + s4;
+                if (mo < mrows) out[static_cast<uint64_t>(mo) * cout + co] = acc[q][j][s4];
+            }
+        }
+}
+
 __global__ void k_sum_chunks(const float *__restrict__ work, int nchunks, uint64_t n, float *__restrict__ out) {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -731,6 +834,24 @@ hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *
     const uint64_t chunk = wgrad_chunk(g.total);
     const unsigned nchunks = static_cast<unsigned>((g.total + chunk - 1) / chunk);
     const int mrows = 27 * cin;
+    if (cin % 8 == 0) {
+        const dim3 grid(static_cast<unsigned>((mrows + kWgRows - 1) / kWgRows), nchunks);
+        const int nt = (cout + 15) / 16;
+        const size_t lds = (static_cast<size_t>(16 * nt) * 32 + static_cast<size_t>(wg_taps(cin)) * cin * 32) *
+                           sizeof(uint16_t);
+        switch (nt) {
+#define LWS_CASE(K) \
+    case K: k_conv_wgrad_lds<K><<<grid, kThreads, lds, s>>>(x, x_shared, cin, dz, cout, work, g, chunk); break;
+            LWS_CASE(1) LWS_CASE(2) LWS_CASE(3) LWS_CASE(4)
+#undef LWS_CASE
+        default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const uint64_t n = static_cast<uint64_t>(mrows) * cout;
+        k_sum_chunks<<<blocks_for(n), kThreads, 0, s>>>(work, static_cast<int>(nchunks), n, dw);
+        return hipGetLastError();
+    }
     constexpr int MT = 2;
     const dim3 grid(static_cast<unsigned>((mrows + 64 * MT - 1) / (64 * MT)), nchunks);
     switch ((cout + 15) / 16) {
