@@ -3,7 +3,8 @@ end on the GPU at a size that runs in seconds: twelve 17^3 side-heated
 cavities (Ra log-uniform on [1e4, 1e5], Pr 0.71) are advanced to steady
 state in one batch, their fields resampled to 17^3 train the network, and a
 held-out cavity (Ra 3e4, not in the training set) is run to the same steady-
-state criterion from rest and from the network's prediction."""
+state criterion from rest and from the network's prediction, plain and
+averaged over the cell's symmetries."""
 import numpy as np
 import pytest
 
@@ -48,11 +49,12 @@ def test_warm_start_reaches_steady_state_in_fewer_steps():
                          log=lambda s: None)
     say(f"[warm start] loss {hist[0]['train_loss']:.3e} -> {hist[-1]['train_loss']:.3e}")
     assert hist[-1]["train_loss"] < 0.05 * hist[0]["train_loss"]
-    r = WS.compare(net, N, 3e4, Pr, storage="fp32", check=500, tol=2e-6, max_steps=200_000, probe=2000,
-                   log=lambda s: None)
-    say(f"[warm start] cold {r['cold']['steps']} steps, warm {r['warm']['steps']} steps, "
-        f"Nu cold {r['cold']['Nu']['Nu_hot']:.5f} warm {r['warm']['Nu']['Nu_hot']:.5f}")
-    assert r["cold"]["converged"] and r["warm"]["converged"]
-    assert r["kept_warm_start"]
-    assert r["warm"]["steps"] <= 0.7 * r["cold"]["steps"]
-    assert abs(r["Nu_rel_diff_warm_vs_cold"]) < 5e-3
+    for sym in (False, True):
+        r = WS.compare(net, N, 3e4, Pr, storage="fp32", check=500, tol=2e-6, max_steps=200_000, probe=2000,
+                       symmetrize=sym, log=lambda s: None)
+        say(f"[warm start] symmetrize={sym}: cold {r['cold']['steps']} steps, warm {r['warm']['steps']} steps, "
+            f"Nu cold {r['cold']['Nu']['Nu_hot']:.5f} warm {r['warm']['Nu']['Nu_hot']:.5f}")
+        assert r["cold"]["converged"] and r["warm"]["converged"]
+        assert r["kept_warm_start"]
+        assert r["warm"]["steps"] <= 0.75 * r["cold"]["steps"]
+        assert abs(r["Nu_rel_diff_warm_vs_cold"]) < 5e-3
