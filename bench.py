@@ -27,8 +27,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 METRIC = "coupled-lattice MLUPS & % HBM roofline; steps-to-steady vs plain at Nu ±0.5%"
 # bytes of one node's 26 populations in HBM (FP16 storage keeps the seven
 # thermal populations in FP32); a step reads and writes each once
-NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 19 * 2 + 7 * 4}
-DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage / f32 compute"}
+NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 19 * 2 + 7 * 4, "fp16c": 19 * 2 + 7 * 4}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage / f32 compute",
+         "fp16c": "custom 16-bit storage / f32 compute"}
 
 
 def parse():
@@ -40,7 +41,7 @@ def parse():
     ap.add_argument("--Ra", type=float, default=1e7)
     ap.add_argument("--Pr", type=float, default=0.71)
     ap.add_argument("--cell", default="side_heated", choices=["side_heated", "rayleigh_benard"])
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s", "fp16c"])
     ap.add_argument("--sample-every", type=int, default=100)
     ap.add_argument("--residual-every", type=int, default=1000)
     ap.add_argument("--block", type=int, default=0)

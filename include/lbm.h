@@ -63,8 +63,11 @@ enum lbm_cell { LBM_SIDE_HEATED = 0, LBM_RAYLEIGH_BENARD = 1 };
  * deviations from the rest equilibrium (f_i - w_i, g_i - w_i^T * 0).
  * FP64: FP64 storage and arithmetic.  FP32: FP32 storage and arithmetic.
  * FP16S: f as FP16 scaled deviations, g as FP32; FP32 arithmetic
- * (66 bytes per node instead of 104). */
-enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 };
+ * (66 bytes per node instead of 104).  FP16C: as FP16S with f in a customised
+ * 16-bit format (sign, 4-bit exponent with bias 18, 11-bit mantissa,
+ * subnormals below 2^-17; |f_i - w_i| must stay below 1/4, larger values
+ * saturate), one mantissa bit more than IEEE half over the deviations' range. */
+enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_FP16C = 3 };
 
 enum lbm_status {
     LBM_OK = 0,

@@ -15,11 +15,11 @@ import torch  # loads the HIP runtime the library links against
 from .build import LIB_PATH
 
 SIDE_HEATED, RAYLEIGH_BENARD = 0, 1
-FP64, FP32, FP16S = 0, 1, 2
+FP64, FP32, FP16S, FP16C = 0, 1, 2, 3
 NRAW, NOBS = 18, 19
 
 CELLS = {"side_heated": SIDE_HEATED, "rayleigh_benard": RAYLEIGH_BENARD}
-STORAGES = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
+STORAGES = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S, "fp16c": FP16C}
 
 RAW_NAMES = ["flux_hot", "flux_cold", "flux_hot_mid", "flux_cold_mid", "grad_hot", "grad_cold",
              "grad_hot_mid", "grad_cold_mid", "u2", "w2", "wT", "uT", "eps_u", "eps_T", "drho2",

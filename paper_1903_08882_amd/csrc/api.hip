@@ -69,7 +69,7 @@ int lbm_derive_params(int N, double Ra, double Pr, int cell, int storage, const 
     if (opts) o = *opts;
     std::memset(out, 0, sizeof *out);
     if (N < 3 || (cell != LBM_SIDE_HEATED && cell != LBM_RAYLEIGH_BENARD) ||
-        (storage != LBM_FP64 && storage != LBM_FP32 && storage != LBM_FP16S) || !finite_pos(Ra) ||
+        (storage != LBM_FP64 && storage != LBM_FP32 && storage != LBM_FP16S && storage != LBM_FP16C) || !finite_pos(Ra) ||
         !finite_pos(Pr) || !finite_pos(o.U) || !std::isfinite(o.T0) || o.sample_every < 0)
         return LBM_EINVAL;
     if (N > lbmk::kMaxN) return LBM_ERANGE;
@@ -107,7 +107,7 @@ int lbm_derive_params(int N, double Ra, double Pr, int cell, int storage, const 
 }
 
 int lbm_state_bytes(int N, int storage, size_t *bytes) {
-    if (!bytes || N < 3 || (storage != LBM_FP64 && storage != LBM_FP32 && storage != LBM_FP16S))
+    if (!bytes || N < 3 || (storage != LBM_FP64 && storage != LBM_FP32 && storage != LBM_FP16S && storage != LBM_FP16C))
         return LBM_EINVAL;
     if (N > lbmk::kMaxN) return LBM_ERANGE;
     *bytes = lbmk::make_layout(N, storage).total;

@@ -71,6 +71,33 @@ __host__ __device__ constexpr double wrest(int i) {
 struct CF64 { using S = double; using W = double; using R = double; static constexpr int GW = 1; };
 struct CF32 { using S = float; using W = float; using R = float; static constexpr int GW = 1; };
 struct CF16 { using S = _Float16; using W = float; using R = float; static constexpr int GW = kQG; };
+struct CF16C { using S = uint16_t; using W = float; using R = float; static constexpr int GW = kQG; };
+
+// The customised 16-bit deviation format of CF16C: sign, 4-bit exponent with
+// bias 18, 11-bit mantissa, subnormals below 2^-17 (spacing 2^-28), no
+// infinities; |v| >= 2^-2 saturates to the largest code.  One more mantissa
+// bit than IEEE half over the range the deviations f_i - w_i occupy.  Both
+// directions are branch-free: the codec runs 38 times per node and step.
+__device__ __forceinline__ uint16_t c16_enc(float v) {
+    const uint32_t b = __float_as_uint(v);
+    const uint32_t a = b & 0x7fffffffu;
+    // |v| >= 2^-17: rebias the exponent (E + 127 -> E + 18) and round the
+    // mantissa to 11 bits, ties to even; a carry moves into the exponent and
+    // anything past the largest code (|v| >= 2^-2, inf, NaN) is clamped to it
+    const uint32_t nrm = min((a + (0x7ffu - (109u << 23)) + ((a >> 12) & 1u)) >> 12, 0x7fffu);
+    // |v| < 2^-17: the nearest multiple of 2^-28, ties to even: |v| 2^28 is
+    // exact, and adding 2^23 rounds it to an integer in the low mantissa bits
+    const uint32_t sub = __float_as_uint(fmaf(__uint_as_float(a), 0x1p28f, 0x1p23f)) - 0x4b000000u;
+    const uint32_t code = a >= (110u << 23) ? nrm : sub;
+    return static_cast<uint16_t>(code | ((b >> 16) & 0x8000u));
+}
+// The code's exponent and mantissa, placed in an FP32 word, read 2^-109 times
+// the value (normal codes as normal floats, subnormal codes as FP32
+// denormals, which the kernels keep): one multiply rescales both.
+__device__ __forceinline__ float c16_dec(uint16_t c) {
+    const uint32_t u = c;
+    return __uint_as_float(((u & 0x7fffu) << 12) | ((u & 0x8000u) << 16)) * 0x1p109f;
+}
 
 // Storage width and byte start (per node of a sub-block) of population q.
 template <class C>
@@ -94,6 +121,8 @@ template <class C>
 __device__ __forceinline__ typename C::R dec(typename C::S v, typename C::R inv_scale) {
     if constexpr (std::is_same<C, CF16>::value)
         return static_cast<float>(v) * inv_scale;
+    else if constexpr (std::is_same<C, CF16C>::value)
+        return c16_dec(v);
     else
         return v;
 }
@@ -101,6 +130,8 @@ template <class C>
 __device__ __forceinline__ typename C::S enc(typename C::R v, typename C::R scale) {
     if constexpr (std::is_same<C, CF16>::value)
         return static_cast<_Float16>(v * scale);
+    else if constexpr (std::is_same<C, CF16C>::value)
+        return c16_enc(v);
     else
         return v;
 }
@@ -981,6 +1012,7 @@ hipError_t with_codec(const lbm_t *h, F &&fn) {
     switch (h->storage) {
     case LBM_FP64: return fn(CF64{});
     case LBM_FP32: return fn(CF32{});
+    case LBM_FP16C: return fn(CF16C{});
     default: return fn(CF16{});
     }
 }
@@ -1080,14 +1112,15 @@ uint32_t lds_cap_bytes(int waves, int block) {
 void default_waves(int storage, int out[2]) {
     // measured on the 257^3 step with streaming canonical-storage accesses:
     // FP32 587 us capped against 604 uncapped, FP16 380 against 383, FP64
-    // 1207 against 1215
+    // 1207 against 1215; the 16-bit format of FP16C spends more ALU on its
+    // codec and runs best uncapped (402 us, 411 under the FP16 caps)
     out[0] = out[1] = 0;
     if (storage == LBM_FP32) {
         out[0] = 2;
         out[1] = 3;
     } else if (storage == LBM_FP16S) {
         out[0] = 3;
-    } else {
+    } else if (storage == LBM_FP64) {
         out[0] = 2;
         out[1] = 2;
     }
@@ -1230,7 +1263,7 @@ Layout make_layout(int N, int storage) {
     // sub-blocks of 32 KB per (moving) population, or one power of two
     // covering the whole plane when that is smaller
     const uint64_t wide = storage == LBM_FP64 ? 8 : 4;   // width of the wide slots
-    const uint64_t nwide = storage == LBM_FP16S ? CF16::GW : 1;
+    const uint64_t nwide = (storage == LBM_FP16S || storage == LBM_FP16C) ? CF16::GW : 1;
     L.bbits = 0;
     while ((uint64_t{1} << L.bbits) * L.esize < 32768 && (uint64_t{1} << L.bbits) < N2) ++L.bbits;
     const uint64_t B = uint64_t{1} << L.bbits;

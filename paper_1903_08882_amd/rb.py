@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--Ra", type=float, default=1e7)
     ap.add_argument("--Pr", type=float, default=0.7)
     ap.add_argument("--storage", nargs="+", default=["fp32", "fp16s"],
-                    choices=["fp32", "fp64", "fp16s"])
+                    choices=["fp32", "fp64", "fp16s", "fp16c"])
     ap.add_argument("--seed", type=int, default=None,
                     help="noise seed (default: base seed + 2 + case index)")
     ap.add_argument("--min-transient", type=float, default=100.0, help="free-fall times")

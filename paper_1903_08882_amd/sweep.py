@@ -22,7 +22,7 @@ from . import binding as B
 from . import synth
 
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 19 * 2 + 7 * 4}
+NODE_BYTES = {"fp64": 26 * 8, "fp32": 26 * 4, "fp16s": 19 * 2 + 7 * 4, "fp16c": 19 * 2 + 7 * 4}
 
 
 def run_sweep(K=64, storage="fp32", check=1000, tol=2e-6, max_steps=300_000, M=65,
@@ -76,7 +76,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--M", type=int, default=65)
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s", "fp16c"])
     ap.add_argument("--check", type=int, default=1000)
     # FP32 storage settles to max |dT| of about 1e-6 per 1000 steps (its
     # rounding floor), so the sweep's default stop is 2e-6

@@ -57,11 +57,11 @@ def main():
     ap.add_argument("--N", type=int, default=129)
     ap.add_argument("--Ra", type=float, default=1e6)
     ap.add_argument("--Pr", type=float, default=0.71)
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s", "fp16c"])
     ap.add_argument("--check", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-steps", type=int, default=2_000_000)
-    ap.add_argument("--start-storage", default=None, choices=["fp32", "fp64", "fp16s"],
+    ap.add_argument("--start-storage", default=None, choices=["fp32", "fp64", "fp16s", "fp16c"],
                     help="reach --start-tol in this storage first, then carry the populations over")
     ap.add_argument("--start-tol", type=float, default=1e-5)
     ap.add_argument("--start-max-steps", type=int, default=2_000_000)

@@ -243,8 +243,8 @@ def main():
     c.add_argument("--N", type=int, default=257)
     c.add_argument("--Ra", type=float, default=1e7)
     c.add_argument("--Pr", type=float, default=0.71)
-    c.add_argument("--storage", default="fp16s", choices=["fp32", "fp64", "fp16s"])
-    c.add_argument("--cold-storage", default=None, choices=["fp32", "fp64", "fp16s"])
+    c.add_argument("--storage", default="fp16s", choices=["fp32", "fp64", "fp16s", "fp16c"])
+    c.add_argument("--cold-storage", default=None, choices=["fp32", "fp64", "fp16s", "fp16c"])
     c.add_argument("--check", type=int, default=1000)
     c.add_argument("--tol", type=float, default=1e-4)
     c.add_argument("--probe", type=int, default=20_000)

@@ -25,7 +25,7 @@ if not torch.cuda.is_available():  # collected on a CPU machine only with -m gpu
 
 from paper_1903_08882_amd import binding as B  # noqa: E402
 
-TOL = {"fp32": 1e-5, "fp64": 1e-12, "fp16s": 8 * 2.0 ** -11}
+TOL = {"fp32": 1e-5, "fp64": 1e-12, "fp16s": 8 * 2.0 ** -11, "fp16c": 8 * 2.0 ** -12}
 CELL = {0: "side_heated", 1: "rayleigh_benard"}
 
 
@@ -94,7 +94,7 @@ class Pair:
 # Populations
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s", "fp16c"])
 def test_side_heated_small_config_200_steps(storage):
     """33^3 side-heated cell, Ra 1e4, Pr 0.71, U = 0.1, fluid at rest with
     seeded +-1e-3 temperature noise; populations after 200 and 201 steps."""
@@ -108,7 +108,7 @@ def test_side_heated_small_config_200_steps(storage):
 
 
 @pytest.mark.parametrize("cell", [0, 1])
-@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s", "fp16c"])
 def test_rich_state_200_steps(cell, storage):
     """A state exciting every moment (rho, u, T random; off-equilibrium
     populations), N = 21 (ragged last block of each plane), both cells."""
@@ -122,7 +122,7 @@ def test_rich_state_200_steps(cell, storage):
 
 
 @pytest.mark.parametrize("N", [3, 4, 8])
-@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s", "fp16c"])
 def test_smallest_and_even_sizes(N, storage):
     pr = Pair(N, 1e4, 7.0, 1, storage, U=0.1)
     pr.init_rich()
@@ -153,7 +153,7 @@ def test_block_sizes_give_identical_results():
             assert np.array_equal(pop, ref), block
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "fp16c"])
 def test_occupancy_caps_give_identical_results(storage):
     """The caps only reserve LDS; every setting computes the same populations."""
     ref = None
@@ -172,7 +172,7 @@ def test_occupancy_caps_give_identical_results(storage):
         B.lbm_create(9, 1e5, 0.71, 0, storage, B.lbm_default_opts(waves_even=9))
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s", "fp16c"])
 def test_set_get_populations_round_trip(storage):
     N = 9
     o = oracle.Oracle(N, 1e4, 0.71, 0, U=0.1)
@@ -185,8 +185,59 @@ def test_set_get_populations_round_trip(storage):
         assert np.abs(got - o.pop).max() < 1e-16
     elif storage == "fp32":
         assert_pop_close(got, o.pop, o.p, 1e-7, "round trip")
-    else:   # one rounding to FP16 of a deviation no larger than its floor
-        assert_pop_close(got, o.pop, o.p, 2.0 ** -11, "round trip")
+    else:   # one rounding to 16 bits of a deviation no larger than its floor
+        assert_pop_close(got, o.pop, o.p, 2.0 ** -11 if storage == "fp16s" else 2.0 ** -12, "round trip")
+
+
+def _c16_table():
+    """Every non-negative value of the 16-bit deviation format, in code order:
+    code e*2^11 + m is m 2^-28 for e = 0 and 2^(e-18) (1 + m 2^-11) above."""
+    e, m = np.divmod(np.arange(1 << 15), 1 << 11)
+    return np.where(e == 0, m * 2.0 ** -28, 2.0 ** (e - 18.0) * (1 + m * 2.0 ** -11))
+
+
+def _c16_nearest(v):
+    """Round to the nearest table value, ties to the even code, saturating."""
+    t = _c16_table()
+    a = np.abs(v)
+    hi = np.clip(np.searchsorted(t, a), 1, len(t) - 1)
+    lo = hi - 1
+    dl, dh = a - t[lo], t[hi] - a
+    code = np.where(dh < dl, hi, lo)
+    code = np.where(dh == dl, np.where(lo % 2 == 0, lo, hi), code)
+    code = np.where(a >= t[-1], len(t) - 1, code)
+    return np.copysign(t[code], v)
+
+
+def test_fp16c_format_rounds_to_nearest_even_exactly():
+    """The 16-bit deviation format against a table of all its values: zero,
+    the spacing 2^-28 below 2^-17, the normal/subnormal edge, ties between
+    neighbouring codes, the largest code and saturation, both signs."""
+    N = 5
+    V = N ** 3
+    rng = np.random.default_rng(5)
+    t = _c16_table()
+    pick = t[rng.integers(1, len(t) - 1, 600)]
+    nxt = t[np.searchsorted(t, pick) + 1]
+    d = np.concatenate([
+        [0.0, 2.0 ** -28, 1.5 * 2.0 ** -28, 2.5 * 2.0 ** -28, 2.0 ** -17, 2.0 ** -17 - 2.0 ** -29,
+         2.0 ** -17 + 2.0 ** -29, 2.0 ** -17 + 3 * 2.0 ** -29, t[-1], 0.5 * (t[-1] + t[-2]),
+         t[-1] + 2.0 ** -20, 0.25, 0.3],
+        pick, 0.5 * (pick + nxt), pick * (1 + 2.0 ** -14),
+        np.exp(rng.uniform(np.log(2.0 ** -32), np.log(0.2), 19 * V)),
+    ])[:19 * V].astype(np.float32).astype(np.float64)
+    d = d * np.where(rng.random(d.size) < 0.5, -1.0, 1.0)
+    _, _, w = oracle.velocities19()
+    pop = np.zeros((26, V))
+    pop[:19] = w[:, None] + d.reshape(19, V)
+    pop[19:] = 0.01
+    h = B.lbm_create(N, 1e4, 0.71, 0, "fp16c", B.lbm_default_opts(U=0.1))
+    B.lbm_set_populations(h, dev(pop))
+    got = B.lbm_get_populations(h).cpu().numpy().reshape(26, -1)[:19]
+    dev32 = (pop[:19] - w[:, None]).astype(np.float32).astype(np.float64)
+    want = _c16_nearest(dev32) + w[:, None]
+    bad = np.nonzero(got != want)
+    assert bad[0].size == 0, (bad[0].size, dev32[bad][:4], got[bad][:4] - w[bad[0][:4]], want[bad][:4])
 
 
 # --------------------------------------------------------------------------
@@ -262,18 +313,19 @@ def test_residual_against_oracle(storage):
         assert abs(g - w) <= tol * abs(w)
 
 
+@pytest.mark.parametrize("storage", ["fp16s", "fp16c"])
 @pytest.mark.parametrize("cell,N,Ra", [(0, 33, 1e4), (1, 17, 1e6)])
-def test_fp16_storage_observables_after_1000_steps(cell, N, Ra):
+def test_fp16_storage_observables_after_1000_steps(cell, N, Ra, storage):
     """FP16 storage against the FP64 oracle on the headline observables after
     1000 steps from rest + noise (measured errors about 1e-3 or below)."""
-    pr = Pair(N, Ra, 0.71, cell, "fp16s", U=0.1)
+    pr = Pair(N, Ra, 0.71, cell, storage, U=0.1)
     pr.init_rest_noise()
     pr.step(1000)
     ndg = B.lbm_nondimensional(B.lbm_get_params(pr.h), B.lbm_observables_raw(pr.h))
     ndo = oracle.nondimensional(pr.p, pr.o.observables_raw())
     for k in ("Nu_hot", "Nu_cold", "Re_rms", "eps_u", "eps_T", "Nu_vol"):
         err = abs(ndg[k] - ndo[k]) / abs(ndo[k])
-        say(f"fp16s {CELL[cell]} N={N}: {k} rel err {err:.2e}")
+        say(f"{storage} {CELL[cell]} N={N}: {k} rel err {err:.2e}")
         assert err < 5e-3, (k, ndg[k], ndo[k])
 
 
@@ -415,7 +467,7 @@ def _rich_uvwT(N, k):
     return synth.rich_fields(N, seed=synth.SEED0 + 300 + k)[1]
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "fp16c"])
 def test_batched_step_equals_single_handles_bitwise(storage):
     """A batch advances each cavity exactly as its own handle would (same
     kernels, same arithmetic): populations equal bit for bit, both parities."""
@@ -543,7 +595,7 @@ def test_autotune_picks_a_candidate_and_caches_it():
     assert bb in (64, 128, 192, 256) and bms > 0
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "fp16c"])
 def test_checkpoint_restart_continues_bit_for_bit(storage, tmp_path):
     """Save after an odd number of steps (swapped AA parity) with time averages
     running, load into a fresh handle, and step both: populations and averages

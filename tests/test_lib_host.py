@@ -75,7 +75,7 @@ def test_parameter_errors():
 
 def test_state_bytes_cover_populations_and_scratch():
     for N, st, es, nb in [(33, "fp32", 4, 104), (257, "fp32", 4, 104), (257, "fp64", 8, 208),
-                          (129, "fp16s", 2, 66)]:
+                          (129, "fp16s", 2, 66), (129, "fp16c", 2, 66)]:
         b = B.lbm_state_bytes(N, st)
         pops = nb * N ** 3
         scratch = (5 + 4) * N ** 3 * 8
