@@ -51,6 +51,8 @@ def parse():
                     help="oracle steps of the CPU baseline sample (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per step-kernel launch, if recorded")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the device-copy reference measured after the run (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -171,6 +173,21 @@ def main():
     }
     del h
     torch.cuda.empty_cache()
+    if a.copy_mib > 0:
+        # the same GPU's device-to-device copy rate, as a practical ceiling
+        src = torch.ones(a.copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 4 * 20 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        out["device_copy"] = {"GB/s": round(copy_gbs, 1), "bytes": 2 * src.numel() * 4,
+                              "step_kernel_frac_of_copy": round(achieved / copy_gbs, 4)}
+        del src, dst
     if a.calibrate_copy:
         n = a.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -1,0 +1,53 @@
+"""Writes c0_steady_oracle.json: the FP64 oracle's steady state of the small
+side-heated configuration (33^3, Ra 1e4, Pr 0.71, U = 0.1, fluid at rest with
+the seeded +-1e-3 temperature noise), run until max|dT| over 1000 steps is
+below 1e-12 (Sec. 3's steady criterion, taken further than its 1e-8 so that
+a GPU run to the same criterion can be compared to ~1e-9).
+
+    python tests/golden/make_c0_steady.py          (about 10-30 min, all cores)
+
+Uses only the oracle and the seeded input generator.
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_1903_08882_amd import synth  # noqa: E402
+
+N, RA, PR, U, TOL, CHECK, MAX_STEPS = 33, 1e4, 0.71, 0.1, 1e-12, 1000, 3_000_000
+
+
+def main():
+    o = oracle.Oracle(N, RA, PR, oracle.SIDE_HEATED, U=U)
+    o.init_fields(synth.rest_with_noise(N, synth.SEED0))
+    t0 = time.time()
+    m = o.macro()
+    steps, hist = 0, []
+    while steps < MAX_STEPS:
+        o.step(CHECK)
+        steps += CHECK
+        m_new = o.macro()
+        r = o.residual(m, m_new)
+        m = m_new
+        if steps % 20000 == 0:
+            hist.append([steps, float(r[0])])
+            print(f"{steps} steps  max|dT| {r[0]:.3e}  {time.time() - t0:.0f} s", flush=True)
+        if r[0] < TOL:
+            break
+    nd = oracle.nondimensional(o.p, o.observables_raw())
+    out = {"config": {"N": N, "Ra": RA, "Pr": PR, "U": U, "cell": "side_heated",
+                      "init": "rest + seeded noise (seed SEED0)", "tol_max_dT_per_1000": TOL},
+           "steps": steps, "max_dT": float(r[0]), "rel_L1_T": float(r[1]), "rel_L2_u": float(r[2]),
+           "nondimensional": {k: float(v) for k, v in nd.items()}, "residual_history": hist}
+    with open(os.path.join(HERE, "c0_steady_oracle.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out["nondimensional"]), flush=True)
+
+
+if __name__ == "__main__":
+    main()

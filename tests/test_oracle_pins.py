@@ -575,3 +575,18 @@ def test_midline_flux_weighting_for_odd_and_even_N(cell, N):
     tol = 1e-12 if cell == oracle.SIDE_HEATED else 3e-3
     for whole, mid in ((0, 2), (1, 3), (4, 6), (5, 7)):
         assert abs(r[mid] - r[whole]) <= tol * abs(r[whole]), (whole, r[whole], r[mid])
+
+
+def test_stored_c0_steady_state_is_steady_and_balanced():
+    """The stored oracle steady state of the small configuration
+    (golden/c0_steady_oracle.json): it met its criterion, the heat entering at
+    the hot wall leaves at the cold wall (link-flux Nu equal to 1e-9, an exact
+    balance at a steady state), the mid-line Nu exceeds the wall average as in
+    every row of Tables 1-2, and the mean temperature stays at the walls' mean."""
+    import json
+    d = json.load(open(os.path.join(GOLDEN, "c0_steady_oracle.json")))
+    nd = d["nondimensional"]
+    assert d["max_dT"] < d["config"]["tol_max_dT_per_1000"]
+    assert abs(nd["Nu_hot"] - nd["Nu_cold"]) < 1e-9 * nd["Nu_hot"]
+    assert nd["Nu_hot_mid"] > nd["Nu_hot"] > 1.0
+    assert abs(nd["mean_T"]) < 1e-9
