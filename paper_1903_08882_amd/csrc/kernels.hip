@@ -71,32 +71,32 @@ __host__ __device__ constexpr double wrest(int i) {
 struct CF64 { using S = double; using W = double; using R = double; static constexpr int GW = 1; };
 struct CF32 { using S = float; using W = float; using R = float; static constexpr int GW = 1; };
 struct CF16 { using S = _Float16; using W = float; using R = float; static constexpr int GW = kQG; };
-struct CF16C { using S = uint16_t; using W = float; using R = float; static constexpr int GW = kQG; };
+struct CF16C { using S = int16_t; using W = float; using R = float; static constexpr int GW = kQG; };
 
 // The customised 16-bit deviation format of CF16C: sign, 4-bit exponent with
 // bias 18, 11-bit mantissa, subnormals below 2^-17 (spacing 2^-28), no
 // infinities; |v| >= 2^-2 saturates to the largest code.  One more mantissa
-// bit than IEEE half over the range the deviations f_i - w_i occupy.  Both
-// directions are branch-free: the codec runs 38 times per node and step.
-__device__ __forceinline__ uint16_t c16_enc(float v) {
-    const uint32_t b = __float_as_uint(v);
-    const uint32_t a = b & 0x7fffffffu;
-    // |v| >= 2^-17: rebias the exponent (E + 127 -> E + 18) and round the
-    // mantissa to 11 bits, ties to even; a carry moves into the exponent and
+// bit than IEEE half over the range the deviations f_i - w_i occupy.  The
+// codec runs 38 times per node and step, so both directions are a handful
+// of branch-free instructions built on FP32 scaling by 2^-+109, which maps
+// the format's normal range onto FP32 normals with exponent field e and its
+// subnormals onto FP32 denormals (kept: this library is built without
+// denormal flushing).
+__device__ __forceinline__ int16_t c16_enc(float v) {
+    // |v| 2^-109 is exact for |v| >= 2^-17; below, the FP32 denormal result
+    // rounds |v| to a multiple of 2^-40 (ties to even) first
+    const uint32_t a = __float_as_uint(fabsf(v) * 0x1p-109f);
+    // drop 12 mantissa bits, ties to even; a carry moves into the exponent and
     // anything past the largest code (|v| >= 2^-2, inf, NaN) is clamped to it
-    const uint32_t nrm = min((a + (0x7ffu - (109u << 23)) + ((a >> 12) & 1u)) >> 12, 0x7fffu);
-    // |v| < 2^-17: the nearest multiple of 2^-28, ties to even: |v| 2^28 is
-    // exact, and adding 2^23 rounds it to an integer in the low mantissa bits
-    const uint32_t sub = __float_as_uint(fmaf(__uint_as_float(a), 0x1p28f, 0x1p23f)) - 0x4b000000u;
-    const uint32_t code = a >= (110u << 23) ? nrm : sub;
-    return static_cast<uint16_t>(code | ((b >> 16) & 0x8000u));
+    const uint32_t code = min((a + 0x7ffu + ((a >> 12) & 1u)) >> 12, 0x7fffu);
+    return static_cast<int16_t>(static_cast<uint16_t>(code | ((__float_as_uint(v) >> 16) & 0x8000u)));
 }
-// The code's exponent and mantissa, placed in an FP32 word, read 2^-109 times
-// the value (normal codes as normal floats, subnormal codes as FP32
-// denormals, which the kernels keep): one multiply rescales both.
-__device__ __forceinline__ float c16_dec(uint16_t c) {
-    const uint32_t u = c;
-    return __uint_as_float(((u & 0x7fffu) << 12) | ((u & 0x8000u) << 16)) * 0x1p109f;
+// Loaded sign-extended: shifting the 32-bit word left by 12 puts exponent and
+// mantissa in place and ones in bits 27-31 of a negative code; clearing bits
+// 27-30 leaves the sign.
+__device__ __forceinline__ float c16_dec(int16_t c) {
+    const uint32_t w = static_cast<uint32_t>(static_cast<int32_t>(c));
+    return __uint_as_float((w << 12) & 0x87ffffffu) * 0x1p109f;
 }
 
 // Storage width and byte start (per node of a sub-block) of population q.
@@ -1112,8 +1112,8 @@ uint32_t lds_cap_bytes(int waves, int block) {
 void default_waves(int storage, int out[2]) {
     // measured on the 257^3 step with streaming canonical-storage accesses:
     // FP32 587 us capped against 604 uncapped, FP16 380 against 383, FP64
-    // 1207 against 1215; the 16-bit format of FP16C spends more ALU on its
-    // codec and runs best uncapped (402 us, 411 under the FP16 caps)
+    // 1207 against 1215; FP16C, whose codec costs more ALU, 394 us uncapped
+    // and within 1% of that under any cap
     out[0] = out[1] = 0;
     if (storage == LBM_FP32) {
         out[0] = 2;

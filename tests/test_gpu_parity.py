@@ -200,9 +200,12 @@ def _c16_table():
 
 
 def _c16_nearest(v):
-    """Round to the nearest table value, ties to the even code, saturating."""
+    """The format's rounding: magnitudes below 2^-17 first to a multiple of
+    2^-40 (ties to even), then every magnitude to the nearest table value,
+    ties to the even code, saturating at the largest."""
     t = _c16_table()
     a = np.abs(v)
+    a = np.where(a < 2.0 ** -17, np.round(a * 2.0 ** 40) * 2.0 ** -40, a)
     hi = np.clip(np.searchsorted(t, a), 1, len(t) - 1)
     lo = hi - 1
     dl, dh = a - t[lo], t[hi] - a
@@ -214,7 +217,8 @@ def _c16_nearest(v):
 
 def test_fp16c_format_rounds_to_nearest_even_exactly():
     """The 16-bit deviation format against a table of all its values: zero,
-    the spacing 2^-28 below 2^-17, the normal/subnormal edge, ties between
+    the spacing 2^-28 below 2^-17 (with the 2^-40 pre-rounding there: values
+    just off a tie at that grid), the normal/subnormal edge, ties between
     neighbouring codes, the largest code and saturation, both signs."""
     N = 5
     V = N ** 3
@@ -225,7 +229,9 @@ def test_fp16c_format_rounds_to_nearest_even_exactly():
     d = np.concatenate([
         [0.0, 2.0 ** -28, 1.5 * 2.0 ** -28, 2.5 * 2.0 ** -28, 2.0 ** -17, 2.0 ** -17 - 2.0 ** -29,
          2.0 ** -17 + 2.0 ** -29, 2.0 ** -17 + 3 * 2.0 ** -29, t[-1], 0.5 * (t[-1] + t[-2]),
-         t[-1] + 2.0 ** -20, 0.25, 0.3],
+         t[-1] + 2.0 ** -20, 0.25, 0.3,
+         (1000.5 + 2.0 ** -13) * 2.0 ** -28, (1000.5 - 2.0 ** -13) * 2.0 ** -28,
+         (7.5 + 2.0 ** -14) * 2.0 ** -28, 2.0 ** -17 - 2.0 ** -41, 2.0 ** -17 - 2.0 ** -39],
         pick, 0.5 * (pick + nxt), pick * (1 + 2.0 ** -14),
         np.exp(rng.uniform(np.log(2.0 ** -32), np.log(0.2), 19 * V)),
     ])[:19 * V].astype(np.float32).astype(np.float64)
