@@ -65,8 +65,11 @@ enum lbm_cell { LBM_SIDE_HEATED = 0, LBM_RAYLEIGH_BENARD = 1 };
  * FP16S: f as FP16 scaled deviations, g as FP32; FP32 arithmetic
  * (66 bytes per node instead of 104).  FP16C: as FP16S with f in a customised
  * 16-bit format (sign, 4-bit exponent with bias 18, 11-bit mantissa,
- * subnormals below 2^-17; |f_i - w_i| must stay below 1/4, larger values
- * saturate), one mantissa bit more than IEEE half over the deviations' range. */
+ * subnormals below 2^-17 spaced 2^-28; round to nearest even, magnitudes
+ * below 2^-17 first rounded to a multiple of 2^-40; |f_i - w_i| must stay
+ * below 1/4, larger values saturate), one mantissa bit more than IEEE half
+ * over the deviations' range (the customised 16-bit storage that Lehmann et
+ * al., Phys. Rev. E 2022, propose for lattice Boltzmann populations). */
 enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2, LBM_FP16C = 3 };
 
 enum lbm_status {

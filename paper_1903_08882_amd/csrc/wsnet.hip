@@ -271,16 +271,18 @@ __global__ __launch_bounds__(kThreads) void k_conv_wgrad(const uint16_t *__restr
 // the neighbour leaves the grid); every MFMA operand is then one 16-byte LDS
 // read, and the global traffic is coalesced 16-byte loads.
 constexpr int kWgRows = 128;
+constexpr int kWgVox = 32;   // voxels staged per barrier (whole MFMA k-steps of 32; 64 was slower for wide layers)
 
 int wg_taps(int cin) { return std::min(27, (kWgRows + cin - 1) / cin + 1); }
 
-template <int NT>
+template <int NT, int GV>
 __global__ __launch_bounds__(kThreads) void k_conv_wgrad_lds(const uint16_t *__restrict__ x, int x_shared, int cin,
                                                              const uint16_t *__restrict__ dz, int cout,
                                                              float *__restrict__ work, Grid g, uint64_t chunk) {
+    static_assert(GV % 32 == 0 && kThreads % GV == 0, "voxel groups are whole MFMA k-steps");
     extern __shared__ uint4 lds_raw[];
-    uint16_t *ldz = reinterpret_cast<uint16_t *>(lds_raw);   // [16 NT][32]
-    uint16_t *lx = ldz + 16 * NT * 32;                       // [taps][cin][32]
+    uint16_t *ldz = reinterpret_cast<uint16_t *>(lds_raw);   // [16 NT][GV]
+    uint16_t *lx = ldz + 16 * NT * GV;                       // [taps][cin][GV]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mrows = 27 * cin;
     const int m0 = blockIdx.x * kWgRows;
@@ -303,52 +305,56 @@ __global__ __launch_bounds__(kThreads) void k_conv_wgrad_lds(const uint16_t *__r
     for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[q][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint64_t u0 = static_cast<uint64_t>(blockIdx.y) * chunk;
-    const uint64_t u1 = u0 + chunk < g.total ? u0 + chunk : g.total;
-    for (uint64_t ub = u0; ub < u1; ub += 32) {
+    const uint32_t u0 = blockIdx.y * static_cast<uint32_t>(chunk);
+    const uint32_t u1 = u0 + chunk < g.total ? static_cast<uint32_t>(u0 + chunk) : static_cast<uint32_t>(g.total);
+    // every element this thread stages belongs to voxel vi of the group
+    const int vi = threadIdx.x % GV;
+    for (uint32_t ub = u0; ub < u1; ub += GV) {
+        const uint32_t u = ub + vi;
+        const bool live = u < u1;
+        const uint32_t b = u / g.V, v = u - b * g.V;
+        const uint32_t qv = v / g.W;
+        const int px = static_cast<int>(v - qv * g.W), py = static_cast<int>(qv % g.H),
+                  pz = static_cast<int>(qv / g.H);
+        const uint16_t *xc = x + (static_cast<uint64_t>(x_shared ? 0 : b * g.V) + v) * cin;
         __syncthreads();                                  // the previous group's reads are done
-        for (int e = threadIdx.x; e < 32 * 16 * NT; e += kThreads) {
-            const int co = e % (16 * NT), vi = e / (16 * NT);
-            const uint64_t u = ub + vi;
-            ldz[co * 32 + vi] = (u < u1 && co < cout) ? dz[u * cout + co] : uint16_t(0);
+        for (int e = threadIdx.x; e < GV * 16 * NT; e += kThreads) {
+            const int co = e % (16 * NT), vj = e / (16 * NT);
+            const uint32_t uj = ub + vj;
+            ldz[co * GV + vj] = (uj < u1 && co < cout) ? dz[static_cast<uint64_t>(uj) * cout + co] : uint16_t(0);
         }
-        for (int e = threadIdx.x; e < ntap * cgroups * 32; e += kThreads) {
-            const int vi = e & 31, rest = e >> 5;
+        for (int e = threadIdx.x; e < ntap * cgroups * GV; e += kThreads) {
+            const int rest = e / GV;
             const int cg = rest % cgroups, tt = rest / cgroups;
             const int t = t_lo + tt;
-            const uint64_t u = ub + vi;
+            const int oz = t / 9 - 1, oy = (t / 3) % 3 - 1, ox = t % 3 - 1;
             uint4 val = {0u, 0u, 0u, 0u};
-            if (u < u1) {
-                const uint64_t b = u / g.V;
-                const uint32_t v = static_cast<uint32_t>(u - b * g.V);
-                const int px = static_cast<int>(v % g.W);
-                const uint32_t qv = v / g.W;
-                const int py = static_cast<int>(qv % g.H), pz = static_cast<int>(qv / g.H);
-                const int nz = pz + t / 9 - 1, ny = py + (t / 3) % 3 - 1, nx = px + t % 3 - 1;
-                if (nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W) {
-                    const uint64_t xb = x_shared ? 0 : b * g.V;
-                    val = *reinterpret_cast<const uint4 *>(
-                        x + (xb + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + 8 * cg);
-                }
-            }
+            if (live && pz + oz >= 0 && pz + oz < g.D && py + oy >= 0 && py + oy < g.H && px + ox >= 0 &&
+                px + ox < g.W)
+                val = *reinterpret_cast<const uint4 *>(
+                    xc + (static_cast<int64_t>((oz * g.H + oy) * g.W + ox)) * cin + 8 * cg);
             const u16x8 h = __builtin_bit_cast(u16x8, val);
-            uint16_t *dst = lx + (tt * cin + 8 * cg) * 32 + vi;
+            uint16_t *dst = lx + (tt * cin + 8 * cg) * GV + vi;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) dst[c * 32] = h[c];
+            for (int c = 0; c < 8; ++c) dst[c * GV] = h[c];
         }
         __syncthreads();
-        bf16x8 bfr[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j)
-            bfr[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ldz + (16 * j + r) * 32 + 8 * grp));
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            uint4 av = {0u, 0u, 0u, 0u};
-            if (mv[q]) av = *reinterpret_cast<const uint4 *>(lx + lrow[q] * 32 + 8 * grp);
-            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+        for (int ks = 0; ks < GV / 32; ++ks) {
+            bf16x8 bfr[NT];
 #pragma unroll
             for (int j = 0; j < NT; ++j)
-                acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[q][j], 0, 0, 0);
+                bfr[j] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(ldz + (16 * j + r) * GV + 32 * ks + 8 * grp));
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                uint4 av = {0u, 0u, 0u, 0u};
+                if (mv[q]) av = *reinterpret_cast<const uint4 *>(lx + lrow[q] * GV + 32 * ks + 8 * grp);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[q][j], 0, 0, 0);
+            }
         }
     }
     float *out = work + static_cast<uint64_t>(blockIdx.y) * mrows * cout;
@@ -376,7 +382,7 @@ __global__ void k_sum_chunks(const float *__restrict__ work, int nchunks, uint64
 
 uint64_t wgrad_chunk(uint64_t total) {
     uint64_t c = (total + 255) / 256;
-    c = (c + 31) / 32 * 32;
+    c = (c + kWgVox - 1) / kWgVox * kWgVox;
     return c < 1024 ? 1024 : c;
 }
 
@@ -834,14 +840,14 @@ hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *
     const uint64_t chunk = wgrad_chunk(g.total);
     const unsigned nchunks = static_cast<unsigned>((g.total + chunk - 1) / chunk);
     const int mrows = 27 * cin;
-    if (cin % 8 == 0) {
+    if (cin % 8 == 0 && g.total + chunk < (uint64_t{1} << 32)) {   // 32-bit voxel indices
         const dim3 grid(static_cast<unsigned>((mrows + kWgRows - 1) / kWgRows), nchunks);
         const int nt = (cout + 15) / 16;
-        const size_t lds = (static_cast<size_t>(16 * nt) * 32 + static_cast<size_t>(wg_taps(cin)) * cin * 32) *
-                           sizeof(uint16_t);
+        const size_t lds = (static_cast<size_t>(16 * nt) * kWgVox +
+                            static_cast<size_t>(wg_taps(cin)) * cin * kWgVox) * sizeof(uint16_t);
         switch (nt) {
 #define LWS_CASE(K) \
-    case K: k_conv_wgrad_lds<K><<<grid, kThreads, lds, s>>>(x, x_shared, cin, dz, cout, work, g, chunk); break;
+    case K: k_conv_wgrad_lds<K, kWgVox><<<grid, kThreads, lds, s>>>(x, x_shared, cin, dz, cout, work, g, chunk); break;
             LWS_CASE(1) LWS_CASE(2) LWS_CASE(3) LWS_CASE(4)
 #undef LWS_CASE
         default: return hipErrorInvalidValue;
