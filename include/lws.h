@@ -3,7 +3,8 @@
  * (log Ra, Pr), that predicts the steady fields of a side-heated cavity, and
  * the kernels it is trained with.  The network is not part of the method of
  * Xu, Shi & Xi (arXiv:1903.08882); it supplies the initial state (Sec. 3 starts
- * from rest) and the paper's steady-state criterion judges it.
+ * from rest), and the paper's steady-state criterion decides when a run
+ * started from it has converged.
  *
  * Precision: convolutions take bfloat16 operands (round to nearest even from
  * FP32) on the gfx950 matrix cores and accumulate in FP32; everything else,
