@@ -275,11 +275,58 @@ constexpr int kWgVox = 32;   // voxels staged per barrier (whole MFMA k-steps of
 
 int wg_taps(int cin) { return std::min(27, (kWgRows + cin - 1) / cin + 1); }
 
+// Four consecutive voxels' 16-byte loads (8 channels each) written to LDS as
+// eight channel rows of four voxels: one 8-byte store per channel instead of
+// four 2-byte ones.
+__device__ __forceinline__ void store_quad_transposed(uint16_t *dst, int ld, const uint4 (&val)[4]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t w0 = val[0][d], w1 = val[1][d], w2 = val[2][d], w3 = val[3][d];
+        uint2 lo, hi;   // channels 2d and 2d + 1
+        lo.x = (w0 & 0xffffu) | (w1 << 16);
+        lo.y = (w2 & 0xffffu) | (w3 << 16);
+        hi.x = (w0 >> 16) | (w1 & 0xffff0000u);
+        hi.y = (w2 >> 16) | (w3 & 0xffff0000u);
+        *reinterpret_cast<uint2 *>(dst + (2 * d) * ld) = lo;
+        *reinterpret_cast<uint2 *>(dst + (2 * d + 1) * ld) = hi;
+    }
+}
+
+// Voxel coordinates, advanced one voxel at a time in the order of the
+// channels-last index (x fastest, then y, z, batch).
+struct Vox {
+    int x, y, z;
+    uint32_t b;
+};
+__device__ __forceinline__ Vox vox_of(uint32_t u, const Grid &g) {
+    Vox p;
+    p.b = u / g.V;
+    const uint32_t v = u - p.b * g.V, q = v / g.W;
+    p.x = static_cast<int>(v - q * g.W);
+    p.y = static_cast<int>(q % g.H);
+    p.z = static_cast<int>(q / g.H);
+    return p;
+}
+__device__ __forceinline__ Vox vox_next(Vox p, const Grid &g) {
+    if (++p.x == g.W) {
+        p.x = 0;
+        if (++p.y == g.H) {
+            p.y = 0;
+            if (++p.z == g.D) {
+                p.z = 0;
+                ++p.b;
+            }
+        }
+    }
+    return p;
+}
+
 template <int NT, int GV>
 __global__ __launch_bounds__(kThreads) void k_conv_wgrad_lds(const uint16_t *__restrict__ x, int x_shared, int cin,
                                                              const uint16_t *__restrict__ dz, int cout,
                                                              float *__restrict__ work, Grid g, uint64_t chunk) {
-    static_assert(GV % 32 == 0 && kThreads % GV == 0, "voxel groups are whole MFMA k-steps");
+    constexpr int NQ = GV / 4;   // voxel quads per group
+    static_assert(GV % 32 == 0 && kThreads % NQ == 0, "voxel groups are whole MFMA k-steps");
     extern __shared__ uint4 lds_raw[];
     uint16_t *ldz = reinterpret_cast<uint16_t *>(lds_raw);   // [16 NT][GV]
     uint16_t *lx = ldz + 16 * NT * GV;                       // [taps][cin][GV]
@@ -307,36 +354,43 @@ __global__ __launch_bounds__(kThreads) void k_conv_wgrad_lds(const uint16_t *__r
         for (int j = 0; j < NT; ++j) acc[q][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint32_t u0 = blockIdx.y * static_cast<uint32_t>(chunk);
     const uint32_t u1 = u0 + chunk < g.total ? static_cast<uint32_t>(u0 + chunk) : static_cast<uint32_t>(g.total);
-    // every element this thread stages belongs to voxel vi of the group
-    const int vi = threadIdx.x % GV;
+    // every element this thread stages belongs to voxel quad vq of the group
+    const int vq = threadIdx.x % NQ;
     for (uint32_t ub = u0; ub < u1; ub += GV) {
-        const uint32_t u = ub + vi;
-        const bool live = u < u1;
-        const uint32_t b = u / g.V, v = u - b * g.V;
-        const uint32_t qv = v / g.W;
-        const int px = static_cast<int>(v - qv * g.W), py = static_cast<int>(qv % g.H),
-                  pz = static_cast<int>(qv / g.H);
-        const uint16_t *xc = x + (static_cast<uint64_t>(x_shared ? 0 : b * g.V) + v) * cin;
+        const uint32_t uq = ub + 4 * vq;
+        Vox p[4];
+        p[0] = vox_of(uq, g);
+#pragma unroll
+        for (int k = 1; k < 4; ++k) p[k] = vox_next(p[k - 1], g);
         __syncthreads();                                  // the previous group's reads are done
-        for (int e = threadIdx.x; e < GV * 16 * NT; e += kThreads) {
-            const int co = e % (16 * NT), vj = e / (16 * NT);
-            const uint32_t uj = ub + vj;
-            ldz[co * GV + vj] = (uj < u1 && co < cout) ? dz[static_cast<uint64_t>(uj) * cout + co] : uint16_t(0);
+        for (int e = threadIdx.x; e < 2 * NT * NQ; e += kThreads) {
+            const int cg = e / NQ;
+            uint4 val[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                val[k] = uint4{0u, 0u, 0u, 0u};
+                if (uq + k < u1 && 8 * cg < cout)
+                    val[k] = *reinterpret_cast<const uint4 *>(dz + static_cast<uint64_t>(uq + k) * cout + 8 * cg);
+            }
+            store_quad_transposed(ldz + (8 * cg) * GV + 4 * vq, GV, val);
         }
-        for (int e = threadIdx.x; e < ntap * cgroups * GV; e += kThreads) {
-            const int rest = e / GV;
+        for (int e = threadIdx.x; e < ntap * cgroups * NQ; e += kThreads) {
+            const int rest = e / NQ;
             const int cg = rest % cgroups, tt = rest / cgroups;
             const int t = t_lo + tt;
             const int oz = t / 9 - 1, oy = (t / 3) % 3 - 1, ox = t % 3 - 1;
-            uint4 val = {0u, 0u, 0u, 0u};
-            if (live && pz + oz >= 0 && pz + oz < g.D && py + oy >= 0 && py + oy < g.H && px + ox >= 0 &&
-                px + ox < g.W)
-                val = *reinterpret_cast<const uint4 *>(
-                    xc + (static_cast<int64_t>((oz * g.H + oy) * g.W + ox)) * cin + 8 * cg);
-            const u16x8 h = __builtin_bit_cast(u16x8, val);
-            uint16_t *dst = lx + (tt * cin + 8 * cg) * GV + vi;
+            uint4 val[4];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) dst[c * GV] = h[c];
+            for (int k = 0; k < 4; ++k) {
+                val[k] = uint4{0u, 0u, 0u, 0u};
+                const int nz = p[k].z + oz, ny = p[k].y + oy, nx = p[k].x + ox;
+                if (uq + k < u1 && nz >= 0 && nz < g.D && ny >= 0 && ny < g.H && nx >= 0 && nx < g.W) {
+                    const uint64_t xb = x_shared ? 0 : static_cast<uint64_t>(p[k].b) * g.V;
+                    val[k] = *reinterpret_cast<const uint4 *>(
+                        x + (xb + (static_cast<uint64_t>(nz) * g.H + ny) * g.W + nx) * cin + 8 * cg);
+                }
+            }
+            store_quad_transposed(lx + (tt * cin + 8 * cg) * GV + 4 * vq, GV, val);
         }
         __syncthreads();
 #pragma unroll
@@ -372,18 +426,39 @@ __global__ __launch_bounds__(kThreads) void k_conv_wgrad_lds(const uint16_t *__r
         }
 }
 
-__global__ void k_sum_chunks(const float *__restrict__ work, int nchunks, uint64_t n, float *__restrict__ out) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Sum of the per-chunk partial weight gradients, in a fixed order: a block
+// takes 32 outputs, its 8 slices of 32 threads add every 8th chunk in FP64,
+// and the 8 slice sums are added in slice order.
+constexpr int kSumOut = 32, kSumSlices = kThreads / kSumOut;
+__global__ __launch_bounds__(kThreads) void k_sum_chunks(const float *__restrict__ work, int nchunks, uint64_t n,
+                                                         float *__restrict__ out) {
+    __shared__ double part[kSumSlices][kSumOut];
+    const int o = threadIdx.x % kSumOut, sl = threadIdx.x / kSumOut;
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kSumOut + o;
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += work[c * n + i];
-    out[i] = static_cast<float>(s);
+    if (i < n)
+        for (int c = sl; c < nchunks; c += kSumSlices) s += work[static_cast<uint64_t>(c) * n + i];
+    part[sl][o] = s;
+    __syncthreads();
+    if (sl == 0 && i < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSumSlices; ++k) t += part[k][o];
+        out[i] = static_cast<float>(t);
+    }
 }
 
-uint64_t wgrad_chunk(uint64_t total) {
-    uint64_t c = (total + 255) / 256;
+// Voxels per chunk of the weight gradient: enough chunks that the launch has
+// about kWgBlocks blocks (each block waits on a gather per voxel group, so
+// occupancy is what hides the latency; 4096 ran the training shapes 1.1-1.9x
+// faster than 512, 8192 no better), at least kWgVox * 16 voxels each.
+constexpr uint64_t kWgBlocks = 4096;
+uint64_t wgrad_chunk(uint64_t total, int cin) {
+    const uint64_t rowblocks = (27 * static_cast<uint64_t>(cin) + kWgRows - 1) / kWgRows;
+    const uint64_t want = std::max<uint64_t>(1, kWgBlocks / rowblocks);
+    uint64_t c = (total + want - 1) / want;
     c = (c + kWgVox - 1) / kWgVox * kWgVox;
-    return c < 1024 ? 1024 : c;
+    return std::max<uint64_t>(c, 16 * kWgVox);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,10 +912,10 @@ hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp
 
 hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *dz, int cout, float *dw,
                       const Grid &g, float *work, hipStream_t s) {
-    const uint64_t chunk = wgrad_chunk(g.total);
+    const uint64_t chunk = wgrad_chunk(g.total, cin);
     const unsigned nchunks = static_cast<unsigned>((g.total + chunk - 1) / chunk);
     const int mrows = 27 * cin;
-    if (cin % 8 == 0 && g.total + chunk < (uint64_t{1} << 32)) {   // 32-bit voxel indices
+    if (cin % 8 == 0 && cout % 8 == 0 && g.total + chunk < (uint64_t{1} << 32)) {   // 32-bit voxel indices
         const dim3 grid(static_cast<unsigned>((mrows + kWgRows - 1) / kWgRows), nchunks);
         const int nt = (cout + 15) / 16;
         const size_t lds = (static_cast<size_t>(16 * nt) * kWgVox +
@@ -855,7 +930,8 @@ hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const uint64_t n = static_cast<uint64_t>(mrows) * cout;
-        k_sum_chunks<<<blocks_for(n), kThreads, 0, s>>>(work, static_cast<int>(nchunks), n, dw);
+        k_sum_chunks<<<static_cast<unsigned>((n + kSumOut - 1) / kSumOut), kThreads, 0, s>>>(
+            work, static_cast<int>(nchunks), n, dw);
         return hipGetLastError();
     }
     constexpr int MT = 2;
@@ -870,12 +946,13 @@ hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint64_t n = static_cast<uint64_t>(mrows) * cout;
-    k_sum_chunks<<<blocks_for(n), kThreads, 0, s>>>(work, static_cast<int>(nchunks), n, dw);
+    k_sum_chunks<<<static_cast<unsigned>((n + kSumOut - 1) / kSumOut), kThreads, 0, s>>>(
+        work, static_cast<int>(nchunks), n, dw);
     return hipGetLastError();
 }
 
 size_t wgrad_work(int cin, int cout, const Grid &g) {
-    const uint64_t chunk = wgrad_chunk(g.total);
+    const uint64_t chunk = wgrad_chunk(g.total, cin);
     const uint64_t nchunks = (g.total + chunk - 1) / chunk;
     return static_cast<size_t>(nchunks) * 27 * cin * cout * sizeof(float);
 }
