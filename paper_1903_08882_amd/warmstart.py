@@ -4,7 +4,8 @@ Boltzmann runs from its prediction and measure steps to steady state against a
 start from rest.
 
     python -m paper_1903_08882_amd.warmstart train --out params.npz
-    python -m paper_1903_08882_amd.warmstart compare --params params.npz --N 257 --Ra 1e7
+    python -m paper_1903_08882_amd.warmstart compare --params params.npz --N 257 --Ra 1e7 \
+        --symmetrize --cold-storage fp32 --ref-nu 16.3927
 
 train: the 64-cavity sweep (``sweep.run_sweep``: N in {33, 49, 65}, Ra
 log-uniform on [1e4, 1e7], Pr in {0.71, 7}, each resampled to M^3 = 65^3),
@@ -19,6 +20,8 @@ the warm run's residual is compared with the cold run's at the same step; if
 it is not smaller the prediction is dropped and the cold run's count stands
 (fall back).  Reports steps, wall time, the hot-wall Nusselt numbers of both
 runs and their relative difference, and the reference value when given.
+The warm run's storage defaults to FP16C (the customised 16-bit format);
+`--cold-storage fp32` makes the cold run the plain FP32 method.
 """
 import argparse
 import json
@@ -168,7 +171,7 @@ def _nu(h):
     return {k: nd[k] for k in ("Nu_hot", "Nu_cold", "Nu_hot_mid", "Nu_hot_fd", "Re_rms")}
 
 
-def compare(net, N, Ra, Pr, storage="fp16s", check=1000, tol=1e-4, max_steps=2_000_000, probe=20_000,
+def compare(net, N, Ra, Pr, storage="fp16c", check=1000, tol=1e-4, max_steps=2_000_000, probe=20_000,
             seed=synth.SEED0 + 1, ref_nu=None, cold_storage=None, runs=None, symmetrize=False, log=print):
     """Cold start in cold_storage (default: storage) against the warm start in
     storage; with a cold_storage other than storage, a cold start in storage
@@ -243,7 +246,7 @@ def main():
     c.add_argument("--N", type=int, default=257)
     c.add_argument("--Ra", type=float, default=1e7)
     c.add_argument("--Pr", type=float, default=0.71)
-    c.add_argument("--storage", default="fp16s", choices=["fp32", "fp64", "fp16s", "fp16c"])
+    c.add_argument("--storage", default="fp16c", choices=["fp32", "fp64", "fp16s", "fp16c"])
     c.add_argument("--cold-storage", default=None, choices=["fp32", "fp64", "fp16s", "fp16c"])
     c.add_argument("--check", type=int, default=1000)
     c.add_argument("--tol", type=float, default=1e-4)
