@@ -171,14 +171,37 @@ def _nu(h):
     return {k: nd[k] for k in ("Nu_hot", "Nu_cold", "Nu_hot_mid", "Nu_hot_fd", "Re_rms")}
 
 
+def _finish(h, N, Ra, Pr, r, finish_storage, check, finish_tol, max_steps, log, tag):
+    """Second stage: carry the populations of h into a handle in
+    finish_storage and continue to finish_tol; steps, wall time and the Nu
+    track of both stages are added up."""
+    pop = B.lbm_get_populations(h)
+    h2 = B.lbm_create(N, Ra, Pr, "side_heated", finish_storage)
+    B.lbm_set_populations(h2, pop)
+    del pop
+    r2 = _run(h2, check, finish_tol, max(max_steps - r["steps"], check), 0, log, f"{tag}/{finish_storage}")
+    r = dict(r)
+    r["stage1"] = {k: r[k] for k in ("steps", "max_dT", "converged", "wall_s")}
+    r["steps"] += r2["steps"]
+    r["wall_s"] += r2["wall_s"]
+    r["max_dT"], r["converged"] = r2["max_dT"], r2["converged"]
+    r["history"] = r["history"] + r2["history"]
+    r["nu_track"] = r["nu_track"] + [(st + r["stage1"]["steps"],) + tuple(v) for st, *v in r2["nu_track"]]
+    return h2, r
+
+
 def compare(net, N, Ra, Pr, storage="fp16c", check=1000, tol=1e-4, max_steps=2_000_000, probe=20_000,
-            seed=synth.SEED0 + 1, ref_nu=None, cold_storage=None, runs=None, symmetrize=False, log=print):
+            seed=synth.SEED0 + 1, ref_nu=None, cold_storage=None, runs=None, symmetrize=False,
+            finish_storage=None, finish_tol=None, log=print):
     """Cold start in cold_storage (default: storage) against the warm start in
     storage; with a cold_storage other than storage, a cold start in storage
-    is run as well ("cold_same") to separate the two effects."""
+    is run as well ("cold_same") to separate the two effects.  With
+    finish_storage, every run continues from its state at tol in that storage
+    to finish_tol (e.g. a 16-bit stage to 1e-4, then FP64 to 1e-8)."""
     cold_storage = cold_storage or storage
     out = {"N": N, "Ra": Ra, "Pr": Pr, "storage": storage, "cold_storage": cold_storage, "check": check,
-           "tol": tol, "probe": probe, "symmetrize": symmetrize}
+           "tol": tol, "probe": probe, "symmetrize": symmetrize, "finish_storage": finish_storage,
+           "finish_tol": finish_tol}
     res = {}
     plan = [("cold", cold_storage), ("warm", storage)]
     if cold_storage != storage:
@@ -195,6 +218,10 @@ def compare(net, N, Ra, Pr, storage="fp16c", check=1000, tol=1e-4, max_steps=2_0
             B.lbm_step(h, 1)
             out["predicted_Nu"] = _nu(h)
         r = _run(h, check, tol, max_steps, probe, log, tag)
+        if finish_storage:
+            h_next, r = _finish(h, N, Ra, Pr, r, finish_storage, check, finish_tol, max_steps, log, tag)
+            B.lbm_destroy(h)
+            h = h_next
         r["Nu"] = _nu(h)
         r["MLUPS"] = N ** 3 * r["steps"] / r["wall_s"] / 1e6
         r["storage"] = st
@@ -254,6 +281,9 @@ def main():
     c.add_argument("--max-steps", type=int, default=2_000_000)
     c.add_argument("--ref-nu", type=float, default=None)
     c.add_argument("--runs", default="", help="comma list of cold,warm,cold_same (default all)")
+    c.add_argument("--finish-storage", default=None, choices=["fp32", "fp64", "fp16s", "fp16c"],
+                   help="continue every run from its state at --tol in this storage")
+    c.add_argument("--finish-tol", type=float, default=1e-8)
     c.add_argument("--symmetrize", action="store_true",
                    help="average the prediction over the side-heated cell's symmetries")
     a = ap.parse_args()
@@ -276,7 +306,8 @@ def main():
         L.lws_net_set_params(net, d["params"])
         r = compare(net, a.N, a.Ra, a.Pr, a.storage, a.check, a.tol, a.max_steps, a.probe,
                     ref_nu=a.ref_nu, cold_storage=a.cold_storage,
-                    runs=[x for x in a.runs.split(",") if x] or None, symmetrize=a.symmetrize, log=say)
+                    runs=[x for x in a.runs.split(",") if x] or None, symmetrize=a.symmetrize,
+                    finish_storage=a.finish_storage, finish_tol=a.finish_tol, log=say)
         print(json.dumps(r), flush=True)
 
 
