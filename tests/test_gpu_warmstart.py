@@ -4,7 +4,8 @@ cavities (Ra log-uniform on [1e4, 1e5], Pr 0.71) are advanced to steady
 state in one batch, their fields resampled to 17^3 train the network, and a
 held-out cavity (Ra 3e4, not in the training set) is run to the same steady-
 state criterion from rest and from the network's prediction, plain and
-averaged over the cell's symmetries."""
+averaged over the cell's symmetries, and once more in two precision stages
+(FP16C, then FP64) against an FP64 start from rest."""
 import numpy as np
 import pytest
 
@@ -58,3 +59,13 @@ def test_warm_start_reaches_steady_state_in_fewer_steps():
         assert r["kept_warm_start"]
         assert r["warm"]["steps"] <= 0.75 * r["cold"]["steps"]
         assert abs(r["Nu_rel_diff_warm_vs_cold"]) < 5e-3
+    # staged precision: a 16-bit stage to 1e-4, then FP64 to 1e-9, against an
+    # FP64 cold start to the same criterion: both reach the same steady state
+    r = WS.compare(net, N, 3e4, Pr, storage="fp16c", cold_storage="fp64", check=500, tol=1e-4,
+                   max_steps=200_000, probe=2000, symmetrize=True, finish_storage="fp64", finish_tol=1e-9,
+                   runs=["cold", "warm"], log=lambda s: None)
+    say(f"[warm start] staged fp16c -> fp64: cold {r['cold']['steps']} steps, warm {r['warm']['steps']} "
+        f"(first stage {r['warm']['stage1']['steps']})")
+    assert r["cold"]["converged"] and r["warm"]["converged"]
+    assert r["warm"]["stage1"]["converged"] and r["warm"]["storage"] == "fp16c"
+    assert abs(r["Nu_rel_diff_warm_vs_cold"]) < 1e-6
