@@ -22,8 +22,27 @@ FLAGS = [
 ]
 
 
+DEMO_SRC = os.path.join(HERE, "examples", "c_abi_demo.c")
+DEMO_PATH = os.path.join(HERE, "c_abi_demo")
+
+
+def build_demo(verbose=False):
+    """The C example (plain C, gcc) against the built library and the HIP runtime."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I" + os.path.join(rocm, "include"), "-I" + os.path.join(ROOT, "include"), DEMO_SRC,
+           "-L" + HERE, "-lp1903lbm", "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", DEMO_PATH]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed on the C example:\n" + r.stdout + r.stderr)
+    return DEMO_PATH
+
+
 def build(verbose=False, extra_flags=()):
-    """Compile every source into LIB_PATH (always recompiles)."""
+    """Compile every source into LIB_PATH (always recompiles), then the C example."""
     tmp = LIB_PATH + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra_flags, *SOURCES, "-o", tmp]
     if verbose:
@@ -32,6 +51,7 @@ def build(verbose=False, extra_flags=()):
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB_PATH)
+    build_demo(verbose)
     return LIB_PATH
 
 

@@ -134,3 +134,21 @@ def test_warm_start_symbols_exported_and_bound():
     assert lws.lws_packed_elems(8, 16, 0) == 16 * 224
     assert lws.lws_packed_elems(48, 16, 1) == 48 * 448
     assert lws.lws_packed_elems(0, 16, 0) == 0
+
+
+def test_headers_compile_as_c_and_the_c_example_builds(tmp_path):
+    """include/lbm.h and include/lws.h are plain C (C11, -Wall -Wextra
+    -Werror); the C example compiles against them and the HIP runtime header."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    inc = os.path.join(root, "include")
+    src = tmp_path / "h.c"
+    src.write_text('#include "lbm.h"\n#include "lws.h"\nint main(void) { return 0; }\n')
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I" + inc, str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    demo = os.path.join(root, "paper_1903_08882_amd", "examples", "c_abi_demo.c")
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                        "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + inc, demo],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
