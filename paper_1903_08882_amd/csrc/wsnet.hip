@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restric
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     int t = (8 * grp) / cin, ci = 8 * grp - t * cin;
-#pragma unroll 2
+#pragma unroll 4
     for (int k0 = 0; k0 < kpad; k0 += 32) {
         const int k = k0 + 8 * grp;
         bf16x8 a[MT];
@@ -895,9 +895,9 @@ __global__ void k_upsample(const float *__restrict__ pred, int M, int ld, int N,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp, int kpad, int cout, float *z,
-                    const Grid &g, hipStream_t s) {
-    constexpr int MT = 2;
+template <int MT>
+hipError_t conv_fwd_mt(const uint16_t *x, int x_shared, int cin, const uint16_t *wp, int kpad, int cout, float *z,
+                       const Grid &g, hipStream_t s) {
     const unsigned nb = static_cast<unsigned>((g.total + 64 * MT - 1) / (64 * MT));
     const int nt = (cout + 15) / 16;
     switch (nt) {
@@ -908,6 +908,15 @@ hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Four 16-voxel tiles per wave keep four gathers in flight per k-step: 1.1-1.4x
+// over two at the training shapes with up to 64 input channels; with more, the
+// longer reduction already hides the latency and two tiles are as fast.
+hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp, int kpad, int cout, float *z,
+                    const Grid &g, hipStream_t s) {
+    return cin <= 64 ? conv_fwd_mt<4>(x, x_shared, cin, wp, kpad, cout, z, g, s)
+                     : conv_fwd_mt<2>(x, x_shared, cin, wp, kpad, cout, z, g, s);
 }
 
 hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *dz, int cout, float *dw,
