@@ -150,6 +150,99 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(const uint16_t *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Convolution forward from an LDS brick (thin inputs): a block computes an
+// 8 x 8 x 4 brick of output voxels of one sample.  It first stages the
+// 10 x 10 x 6 input brick with its one-voxel halo (zeros outside the grid,
+// channels-last, cin <= kBrickCin) in LDS, so every tap of every output voxel
+// is a 16-byte LDS read: one global load per input voxel and channel group
+// instead of 27 gathers.  Wave w owns output layer z0 + w: four MFMA row
+// tiles of 16 voxels (8 along x by 2 along y).
+// ---------------------------------------------------------------------------
+constexpr int kBrickX = 8, kBrickY = 8, kBrickZ = 4;
+constexpr int kHaloX = kBrickX + 2, kHaloY = kBrickY + 2, kHaloZ = kBrickZ + 2;
+constexpr int kHaloVox = kHaloX * kHaloY * kHaloZ;
+constexpr int kBrickCin = 48;   // 600 voxels x 48 channels x 2 bytes = 57.6 KB of LDS
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_conv_fwd_brick(const uint16_t *__restrict__ x, int x_shared, int cin,
+                                                             const uint16_t *__restrict__ wp, int kpad, int cout,
+                                                             float *__restrict__ z, Grid g, int nbx, int nby) {
+    static_assert(kBrickZ * 64 == kThreads, "one wave per output layer");
+    extern __shared__ uint4 lds_raw[];
+    uint16_t *lx = reinterpret_cast<uint16_t *>(lds_raw);   // [kHaloVox][cin]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int bb = blockIdx.x;
+    const int bxi = bb % nbx, byi = (bb / nbx) % nby, bzi = bb / (nbx * nby);
+    const int x0 = bxi * kBrickX, y0 = byi * kBrickY, z0 = bzi * kBrickZ;
+    const uint32_t b = blockIdx.y;
+    const uint64_t xb = x_shared ? 0 : static_cast<uint64_t>(b) * g.V;
+    const int cg = cin / 8;
+    for (int e = threadIdx.x; e < kHaloVox * cg; e += kThreads) {
+        const int hv = e / cg, c8 = e - hv * cg;
+        const int hx = hv % kHaloX, hy = (hv / kHaloX) % kHaloY, hz = hv / (kHaloX * kHaloY);
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        uint4 val = {0u, 0u, 0u, 0u};
+        if (gx >= 0 && gx < g.W && gy >= 0 && gy < g.H && gz >= 0 && gz < g.D)
+            val = *reinterpret_cast<const uint4 *>(
+                x + (xb + (static_cast<uint64_t>(gz) * g.H + gy) * g.W + gx) * cin + 8 * c8);
+        *reinterpret_cast<uint4 *>(lx + hv * cin + 8 * c8) = val;
+    }
+    __syncthreads();
+    const int r = lane & 15, grp = lane >> 4;
+    // halo index of this lane's output voxel in tile m, before the tap offset
+    int hbase[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        hbase[m] = ((wave + 1) * kHaloY + (2 * m + r / 8 + 1)) * kHaloX + (r % 8 + 1);
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int t = (8 * grp) / cin, ci = 8 * grp - t * cin;
+#pragma unroll 4
+    for (int k0 = 0; k0 < kpad; k0 += 32) {
+        const int k = k0 + 8 * grp;
+        const int off = ((t / 9 - 1) * kHaloY + ((t / 3) % 3 - 1)) * kHaloX + (t % 3 - 1);
+        bf16x8 a[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            uint4 av = {0u, 0u, 0u, 0u};
+            if (t < 27) av = *reinterpret_cast<const uint4 *>(lx + (hbase[m] + off) * cin + ci);
+            a[m] = __builtin_bit_cast(bf16x8, av);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const uint4 bv = *reinterpret_cast<const uint4 *>(wp + static_cast<uint64_t>(16 * j + r) * kpad + k);
+            const bf16x8 bw = __builtin_bit_cast(bf16x8, bv);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bw, acc[m][j], 0, 0, 0);
+        }
+        ci += 32;
+        while (ci >= cin) {
+            ci -= cin;
+            ++t;
+        }
+    }
+    const int oz = z0 + wave;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int row = 4 * grp + s4;
+            const int ox = x0 + row % 8, oy = y0 + 2 * m + row / 8;
+            if (ox >= g.W || oy >= g.H || oz >= g.D) continue;
+            const uint64_t vo = static_cast<uint64_t>(b) * g.V + (static_cast<uint64_t>(oz) * g.H + oy) * g.W + ox;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int co = 16 * j + r;
+                if (co < cout) z[vo * cout + co] = acc[m][j][s4];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient: rows m = t cin + ci, columns co, reduction over voxels in
 // chunks (blockIdx.y); partial tiles go to work[chunk][m][co].  A wave owns MT
 // row tiles, so each dz fragment feeds MT MFMAs; voxel coordinates advance
@@ -915,6 +1008,20 @@ hipError_t conv_fwd_mt(const uint16_t *x, int x_shared, int cin, const uint16_t 
 // longer reduction already hides the latency and two tiles are as fast.
 hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp, int kpad, int cout, float *z,
                     const Grid &g, hipStream_t s) {
+    if (cin % 8 == 0 && cin <= kBrickCin && g.B <= 65535) {
+        const int nbx = (g.W + kBrickX - 1) / kBrickX, nby = (g.H + kBrickY - 1) / kBrickY,
+                  nbz = (g.D + kBrickZ - 1) / kBrickZ;
+        const dim3 grid(static_cast<unsigned>(nbx * nby * nbz), static_cast<unsigned>(g.B));
+        const size_t lds = static_cast<size_t>(kHaloVox) * cin * sizeof(uint16_t);
+        switch ((cout + 15) / 16) {
+#define LWS_CASE(K) \
+    case K: k_conv_fwd_brick<K><<<grid, kThreads, lds, s>>>(x, x_shared, cin, wp, kpad, cout, z, g, nbx, nby); break;
+            LWS_CASE(1) LWS_CASE(2) LWS_CASE(3) LWS_CASE(4) LWS_CASE(5) LWS_CASE(6) LWS_CASE(7) LWS_CASE(8)
+#undef LWS_CASE
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     return cin <= 64 ? conv_fwd_mt<4>(x, x_shared, cin, wp, kpad, cout, z, g, s)
                      : conv_fwd_mt<2>(x, x_shared, cin, wp, kpad, cout, z, g, s);
 }
