@@ -180,14 +180,23 @@ def _finish(h, N, Ra, Pr, r, finish_storage, check, finish_tol, max_steps, log, 
     B.lbm_set_populations(h2, pop)
     del pop
     r2 = _run(h2, check, finish_tol, max(max_steps - r["steps"], check), 0, log, f"{tag}/{finish_storage}")
-    r = dict(r)
-    r["stage1"] = {k: r[k] for k in ("steps", "max_dT", "converged", "wall_s")}
-    r["steps"] += r2["steps"]
-    r["wall_s"] += r2["wall_s"]
+    return h2, merge_stages(r, r2)
+
+
+def merge_stages(r1, r2):
+    """One run record from two consecutive stages: steps and wall time add
+    up, the residual and convergence are the second stage's, the probe stays
+    the first stage's, the residual histories are concatenated and the second
+    stage's Nu track is shifted by the first stage's steps.  The first stage's
+    own figures are kept under "stage1"."""
+    r = dict(r1)
+    r["stage1"] = {k: r1[k] for k in ("steps", "max_dT", "converged", "wall_s")}
+    r["steps"] = r1["steps"] + r2["steps"]
+    r["wall_s"] = r1["wall_s"] + r2["wall_s"]
     r["max_dT"], r["converged"] = r2["max_dT"], r2["converged"]
-    r["history"] = r["history"] + r2["history"]
-    r["nu_track"] = r["nu_track"] + [(st + r["stage1"]["steps"],) + tuple(v) for st, *v in r2["nu_track"]]
-    return h2, r
+    r["history"] = list(r1["history"]) + list(r2["history"])
+    r["nu_track"] = list(r1["nu_track"]) + [(st + r1["steps"],) + tuple(v) for st, *v in r2["nu_track"]]
+    return r
 
 
 def compare(net, N, Ra, Pr, storage="fp16c", check=1000, tol=1e-4, max_steps=2_000_000, probe=20_000,

@@ -1,11 +1,11 @@
-"""Host-side logic of the warm-start driver (no GPU): the fall-back rule and
-the Nu settling measure."""
+"""Host-side logic of the warm-start driver (no GPU): the fall-back rule, the
+Nu settling measure and the record of a run made in two precision stages."""
 import math
 
 import pytest
 
 torch = pytest.importorskip("torch")
-from paper_1903_08882_amd.warmstart import keep_warm_start, steps_to_nu  # noqa: E402
+from paper_1903_08882_amd.warmstart import keep_warm_start, merge_stages, steps_to_nu  # noqa: E402
 
 
 def test_fallback_keeps_warm_start_only_when_its_probe_residual_is_lower():
@@ -25,3 +25,20 @@ def test_steps_to_nu_counts_from_the_last_entry_into_the_band():
     assert steps_to_nu(track, ref, 5e-3, wall="mean") == 40     # means 8.1, 10.04, 10.15, 10.005, 10.005
     assert steps_to_nu(track, ref, 1e-4, wall="hot") is None
     assert steps_to_nu([(5, 10.0)], ref) == 5                   # hot-only tracks
+
+
+def test_two_stage_record_adds_steps_and_shifts_the_second_nu_track():
+    r1 = {"steps": 68000, "max_dT": 9e-5, "converged": True, "wall_s": 3.0, "probe": (20000, 1e-2),
+          "history": [1e-2, 9e-5], "nu_track": [(20000, 9.0, 8.0), (68000, 8.7, 8.6)]}
+    r2 = {"steps": 210000, "max_dT": 9e-9, "converged": True, "wall_s": 29.0, "probe": (1000, 8e-5),
+          "history": [8e-5, 9e-9], "nu_track": [(10000, 8.671, 8.670), (210000, 8.6708, 8.6708)]}
+    r = merge_stages(r1, r2)
+    assert r["steps"] == 278000 and r["wall_s"] == 32.0
+    assert r["max_dT"] == 9e-9 and r["converged"]
+    assert r["probe"] == (20000, 1e-2)                              # the fall-back rule sees stage 1
+    assert r["stage1"] == {"steps": 68000, "max_dT": 9e-5, "converged": True, "wall_s": 3.0}
+    assert r["history"] == [1e-2, 9e-5, 8e-5, 9e-9]
+    assert [row[0] for row in r["nu_track"]] == [20000, 68000, 78000, 278000]
+    assert r["nu_track"][2] == (78000, 8.671, 8.670)
+    assert steps_to_nu(r["nu_track"], 8.6708, 1e-3, wall="mean") == 78000
+    assert r1["steps"] == 68000 and len(r1["nu_track"]) == 2       # inputs left unchanged
