@@ -614,11 +614,14 @@ __global__ void k_film_params(const float *__restrict__ gw, const float *__restr
 
 __device__ __forceinline__ float sigm(float y) { return 1.f / (1.f + __expf(-y)); }
 
+// I: the index type, 32-bit whenever every index of the launch fits (the
+// divisions below are then 32-bit ones, several times cheaper than 64-bit)
+template <class I>
 __global__ void k_film_act(const float *__restrict__ z, int C, Grid g, const float *__restrict__ scale,
                            const float *__restrict__ shift, uint16_t *__restrict__ out, int ostride, int ooff) {
-    const uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= g.total * C) return;
-    const uint64_t u = e / C;
+    const I e = static_cast<I>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= static_cast<I>(g.total) * C) return;
+    const I u = e / C;
     const int c = static_cast<int>(e - u * C);
     const int b = static_cast<int>(u / g.V);
     const float y = z[e] * scale[b * C + c] + shift[b * C + c];
@@ -638,9 +641,11 @@ __global__ __launch_bounds__(kThreads) void k_film_bwd(const float *__restrict__
     const int c = threadIdx.x % C;
     const float sc = scale[b * C + c], sh = shift[b * C + c];
     double a1 = 0.0, a2 = 0.0;
-    for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x; e < n;
-         e += static_cast<uint64_t>(kThreads) * gridDim.x) {
-        const uint64_t u = static_cast<uint64_t>(b) * g.V + e / C;
+    // the stride is a multiple of C, so the voxel advances by stride / C
+    const uint64_t step = static_cast<uint64_t>(kThreads) * gridDim.x;
+    uint64_t e = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    uint64_t u = static_cast<uint64_t>(b) * g.V + e / C;
+    for (; e < n; e += step, u += step / C) {
         const float zz = z[u * C + c];
         const float y = zz * sc + sh;
         const float s = sigm(y);
@@ -730,43 +735,45 @@ __global__ void k_restrict_adj_add(const float *__restrict__ gc, int C, int nf, 
 }
 
 // fine node x of 2n - 1: coarse x/2 (even) or the mean of x/2 and x/2 + 1 (odd)
+template <class I>
 __global__ void k_prolong(const uint16_t *__restrict__ in, int C, int nc, int B, uint16_t *__restrict__ out,
                           int ostride, int ooff) {
     const int nf = 2 * nc - 1;
-    const uint64_t Vc = static_cast<uint64_t>(nc) * nc * nc, Vf = static_cast<uint64_t>(nf) * nf * nf;
-    const uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const I Vc = static_cast<I>(nc) * nc * nc, Vf = static_cast<I>(nf) * nf * nf;
+    const I e = static_cast<I>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= B * Vf * C) return;
-    const uint64_t uf = e / C;
+    const I uf = e / C;
     const int c = static_cast<int>(e - uf * C);
-    const uint64_t b = uf / Vf;
-    const uint64_t v = uf - b * Vf;
+    const I b = uf / Vf;
+    const I v = uf - b * Vf;
     const int x = static_cast<int>(v % nf), y = static_cast<int>((v / nf) % nf),
-              z = static_cast<int>(v / (static_cast<uint64_t>(nf) * nf));
+              z = static_cast<int>(v / (static_cast<I>(nf) * nf));
     const int xo = x & 1, yo = y & 1, zo = z & 1;
     const float w = (xo ? 0.5f : 1.f) * (yo ? 0.5f : 1.f) * (zo ? 0.5f : 1.f);
     float s = 0.f;
     for (int dz = 0; dz <= zo; ++dz)
         for (int dy = 0; dy <= yo; ++dy)
             for (int dx = 0; dx <= xo; ++dx) {
-                const uint64_t cv = ((static_cast<uint64_t>(z / 2 + dz) * nc) + (y / 2 + dy)) * nc + (x / 2 + dx);
+                const I cv = ((static_cast<I>(z / 2 + dz) * nc) + (y / 2 + dy)) * nc + (x / 2 + dx);
                 s += from_bf16(in[(b * Vc + cv) * C + c]);
             }
     out[uf * ostride + ooff + c] = to_bf16(w * s);
 }
 
 // adjoint of k_prolong: coarse i collects fine 2i (1) and 2i -/+ 1 (1/2) per axis
+template <class I>
 __global__ void k_prolong_adj(const float *__restrict__ gf, int gstride, int goff, int C, int nc, int B,
                               float *__restrict__ out) {
     const int nf = 2 * nc - 1;
-    const uint64_t Vc = static_cast<uint64_t>(nc) * nc * nc, Vf = static_cast<uint64_t>(nf) * nf * nf;
-    const uint64_t e = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const I Vc = static_cast<I>(nc) * nc * nc, Vf = static_cast<I>(nf) * nf * nf;
+    const I e = static_cast<I>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= B * Vc * C) return;
-    const uint64_t uc = e / C;
+    const I uc = e / C;
     const int c = static_cast<int>(e - uc * C);
-    const uint64_t b = uc / Vc;
-    const uint64_t v = uc - b * Vc;
+    const I b = uc / Vc;
+    const I v = uc - b * Vc;
     const int i = static_cast<int>(v % nc), j = static_cast<int>((v / nc) % nc),
-              k = static_cast<int>(v / (static_cast<uint64_t>(nc) * nc));
+              k = static_cast<int>(v / (static_cast<I>(nc) * nc));
     float s = 0.f;
     for (int dz = -1; dz <= 1; ++dz) {
         const int fz = 2 * k + dz;
@@ -780,7 +787,7 @@ __global__ void k_prolong_adj(const float *__restrict__ gf, int gstride, int gof
                 const int fx = 2 * i + dx;
                 if (fx < 0 || fx >= nf) continue;
                 const float wx = dx ? 0.5f : 1.f;
-                const uint64_t f = b * Vf + (static_cast<uint64_t>(fz) * nf + fy) * nf + fx;
+                const I f = b * Vf + (static_cast<I>(fz) * nf + fy) * nf + fx;
                 s += wz * wy * wx * gf[f * gstride + goff + c];
             }
         }
@@ -1173,6 +1180,28 @@ hipError_t pack_all(lws_net_t *n, hipStream_t s) {
 float *sc_of(lws_net_t *n, int l) { return n->scale + static_cast<size_t>(l) * n->maxB * 64; }
 float *sh_of(lws_net_t *n, int l) { return n->shift + static_cast<size_t>(l) * n->maxB * 64; }
 
+bool fits32(uint64_t n) { return n < (uint64_t{1} << 32); }
+
+// Interpolation from level nc^3 to (2 nc - 1)^3 and its adjoint, with 32-bit
+// indices when every index of the launch fits.
+void prolong(const uint16_t *in, int C, int nc, int B, uint16_t *out, int ostride, int ooff, hipStream_t s) {
+    const uint64_t nf = 2 * static_cast<uint64_t>(nc) - 1, nfine = B * nf * nf * nf;
+    const unsigned blocks = blocks_for(nfine * C);
+    if (fits32(nfine * std::max(C, ostride)))
+        k_prolong<uint32_t><<<blocks, kThreads, 0, s>>>(in, C, nc, B, out, ostride, ooff);
+    else
+        k_prolong<uint64_t><<<blocks, kThreads, 0, s>>>(in, C, nc, B, out, ostride, ooff);
+}
+void prolong_adj(const float *gf, int gstride, int goff, int C, int nc, int B, float *out, hipStream_t s) {
+    const uint64_t nf = 2 * static_cast<uint64_t>(nc) - 1, nfine = B * nf * nf * nf,
+                   ncoarse = B * static_cast<uint64_t>(nc) * nc * nc;
+    const unsigned blocks = blocks_for(ncoarse * C);
+    if (fits32(nfine * gstride) && fits32(ncoarse * C))
+        k_prolong_adj<uint32_t><<<blocks, kThreads, 0, s>>>(gf, gstride, goff, C, nc, B, out);
+    else
+        k_prolong_adj<uint64_t><<<blocks, kThreads, 0, s>>>(gf, gstride, goff, C, nc, B, out);
+}
+
 // conv + FiLM + SiLU of layer l into out (stride, offset)
 hipError_t layer_fwd(lws_net_t *n, int l, const uint16_t *x, int x_shared, int B, uint16_t *out, int ostride,
                      int ooff, hipStream_t s) {
@@ -1180,8 +1209,12 @@ hipError_t layer_fwd(lws_net_t *n, int l, const uint16_t *x, int x_shared, int B
     const Grid g = make_grid(level_grid(n, B, y.level));
     hipError_t e = conv_fwd(x, x_shared, y.cin, n->packed + y.pf, y.kpf, y.cout, n->Z[l], g, s);
     if (e != hipSuccess) return e;
-    k_film_act<<<blocks_for(g.total * y.cout), kThreads, 0, s>>>(n->Z[l], y.cout, g, sc_of(n, l), sh_of(n, l),
-                                                                  out, ostride, ooff);
+    if (fits32(g.total * std::max(y.cout, ostride)))
+        k_film_act<uint32_t><<<blocks_for(g.total * y.cout), kThreads, 0, s>>>(n->Z[l], y.cout, g, sc_of(n, l),
+                                                                            sh_of(n, l), out, ostride, ooff);
+    else
+        k_film_act<uint64_t><<<blocks_for(g.total * y.cout), kThreads, 0, s>>>(n->Z[l], y.cout, g, sc_of(n, l),
+                                                                            sh_of(n, l), out, ostride, ooff);
     return hipGetLastError();
 }
 
@@ -1247,11 +1280,9 @@ hipError_t forward(lws_net_t *n, int B, hipStream_t s) {
                                                                                      n->n[1], B, n->inE3a);
     if ((e = layer_fwd(n, E3a, n->inE3a, 0, B, n->aE3a, c3, 0, s)) != hipSuccess) return e;
     if ((e = layer_fwd(n, E3b, n->aE3a, 0, B, n->s3, c3, 0, s)) != hipSuccess) return e;
-    k_prolong<<<blocks_for(static_cast<uint64_t>(B) * n->V[1] * c3), kThreads, 0, s>>>(n->s3, c3, n->n[2], B,
-                                                                                    n->cat2, c3 + c2, 0);
+    prolong(n->s3, c3, n->n[2], B, n->cat2, c3 + c2, 0, s);
     if ((e = layer_fwd(n, D2, n->cat2, 0, B, n->aD2, c2, 0, s)) != hipSuccess) return e;
-    k_prolong<<<blocks_for(static_cast<uint64_t>(B) * n->V[0] * c2), kThreads, 0, s>>>(n->aD2, c2, n->n[1], B,
-                                                                                    n->cat1, c2 + c1, 0);
+    prolong(n->aD2, c2, n->n[1], B, n->cat1, c2 + c1, 0, s);
     if ((e = layer_fwd(n, D1, n->cat1, 0, B, n->aD1, c1, 0, s)) != hipSuccess) return e;
     const Layer &o = n->L[OUT];
     const Grid g0 = make_grid(level_grid(n, B, 0));
@@ -1274,11 +1305,9 @@ hipError_t backward(lws_net_t *n, int B, hipStream_t s) {
     if ((e = conv_fwd(n->doutb, 0, o.cout, n->packed + o.pd, o.kpd, o.cin, n->dA, g0, s)) != hipSuccess) return e;
     // decoder
     if ((e = layer_bwd(n, D1, n->dA, c1, 0, n->cat1, 0, B, n->dcat1, s)) != hipSuccess) return e;
-    k_prolong_adj<<<blocks_for(static_cast<uint64_t>(B) * n->V[1] * c2), kThreads, 0, s>>>(
-        n->dcat1, c2 + c1, 0, c2, n->n[1], B, n->dA2);
+    prolong_adj(n->dcat1, c2 + c1, 0, c2, n->n[1], B, n->dA2, s);
     if ((e = layer_bwd(n, D2, n->dA2, c2, 0, n->cat2, 0, B, n->dcat2, s)) != hipSuccess) return e;
-    k_prolong_adj<<<blocks_for(static_cast<uint64_t>(B) * n->V[2] * c3), kThreads, 0, s>>>(
-        n->dcat2, c3 + c2, 0, c3, n->n[2], B, n->dA);
+    prolong_adj(n->dcat2, c3 + c2, 0, c3, n->n[2], B, n->dA, s);
     // level 2
     if ((e = layer_bwd(n, E3b, n->dA, c3, 0, n->aE3a, 0, B, n->dA2, s)) != hipSuccess) return e;
     if ((e = layer_bwd(n, E3a, n->dA2, c3, 0, n->inE3a, 0, B, n->dIn, s)) != hipSuccess) return e;
