@@ -1299,8 +1299,12 @@ hipError_t backward(lws_net_t *n, int B, hipStream_t s) {
     const Grid g0 = make_grid(level_grid(n, B, 0));
     // output layer: weights, bias, input gradient
     if ((e = conv_wgrad(n->aD1, 0, o.cin, n->doutb, o.cout, gp(n, o.oW), g0, n->work, s)) != hipSuccess) return e;
-    k_chan_partial<<<n->nbx, kThreads, 0, s>>>(n->dout, o.cout, g0.total, n->part);
-    k_chan_final<<<1, 64, 0, s>>>(n->part, n->nbx, o.cout, gp(n, o.ob));
+    // bias gradient: enough blocks to stream dout at full rate (64 blocks ran
+    // at ~0.2 TB/s), within the partial buffer
+    const size_t part_cap = static_cast<size_t>(n->maxB) * n->nbx * 2 * 64 + 4096;
+    const int nbc = static_cast<int>(std::min<size_t>(1024, part_cap / o.cout));
+    k_chan_partial<<<nbc, kThreads, 0, s>>>(n->dout, o.cout, g0.total, n->part);
+    k_chan_final<<<1, 64, 0, s>>>(n->part, nbc, o.cout, gp(n, o.ob));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = conv_fwd(n->doutb, 0, o.cout, n->packed + o.pd, o.kpd, o.cin, n->dA, g0, s)) != hipSuccess) return e;
     // decoder
