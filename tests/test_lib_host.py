@@ -152,3 +152,28 @@ def test_headers_compile_as_c_and_the_c_example_builds(tmp_path):
                         "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + inc, demo],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_product_code_never_reaches_the_oracle():
+    """The package (Python and HIP sources) neither imports, loads nor names
+    the oracle: only tests, smoke() and the bench's CPU baseline use it."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_1903_08882_amd")
+    offenders = []
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if not f.endswith((".py", ".hip", ".h", ".c")):
+                continue
+            text = open(os.path.join(dirpath, f)).read()
+            if re.search(r"^\s*(import|from)\s+oracle\b|orc_|liborc|oracle\.c", text, re.M):
+                offenders.append(f)
+    assert not offenders, offenders
+
+
+def test_hip_build_disables_packed_fp32_instructions():
+    """Every HIP compile of the library passes the flag that keeps packed FP32
+    instructions out of the generated code."""
+    from paper_1903_08882_amd import build as BUILD
+    flags = " ".join(BUILD.FLAGS)
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
+    assert "--offload-arch=gfx950" in flags
