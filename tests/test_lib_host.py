@@ -177,3 +177,18 @@ def test_hip_build_disables_packed_fp32_instructions():
     flags = " ".join(BUILD.FLAGS)
     assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
     assert "--offload-arch=gfx950" in flags
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus N > 1 (or WORLD_SIZE > 1) exits with
+    status 2 and says why, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+    env = dict(os.environ, WORLD_SIZE="4")
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py")], capture_output=True, text=True,
+                       timeout=60, env=env)
+    assert r.returncode == 2 and r.stdout == ""
