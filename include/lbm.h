@@ -133,8 +133,8 @@ typedef struct {
                          64 in [64, 1024]; 0 = library default                */
     int waves_even;   /* occupancy cap of the step kernel, waves per SIMD, for
                          even and odd steps: 1..8, 0 = library default for the
-                         storage type (FP32: 2 and 3; FP16: 3 and none; FP64:
-                         2 and 2), -1 = no cap.  The cap reserves otherwise unused
+                         storage type (FP32: 2 and 3; FP16S: 3 and none; FP16C:
+                         none and none; FP64: 2 and 2), -1 = no cap.  The cap reserves otherwise unused
                          LDS per block; fewer concurrent waves per SIMD spread
                          fewer HBM streams and measured faster for these steps */
     int waves_odd;
