@@ -590,3 +590,46 @@ def test_stored_c0_steady_state_is_steady_and_balanced():
     assert abs(nd["Nu_hot"] - nd["Nu_cold"]) < 1e-9 * nd["Nu_hot"]
     assert nd["Nu_hot_mid"] > nd["Nu_hot"] > 1.0
     assert abs(nd["mean_T"]) < 1e-9
+
+
+def _channel(p, n, T1, steps):
+    """Flow between two no-slip walls at x = 0 and x = n (half-way bounce-back),
+    uniform in y and z, driven along z by the buoyancy of a uniform temperature
+    T1 (g kept at its equilibrium), with the oracle's collision at each node
+    and plain streaming along x.  Returns the velocity at the n nodes."""
+    e, opp, _ = oracle.velocities19()
+    f = np.array([oracle.feq(1.0, [0.0, 0.0, 0.0]) for _ in range(n)])
+    u = np.zeros((n, 3))
+    for _ in range(steps):
+        fp = np.array([oracle.collide(p, f[i], oracle.geq(p, T1, u[i]))[0] for i in range(n)])
+        f = np.empty_like(fp)
+        for i in range(n):
+            for q in range(19):
+                j = i + e[q, 0]
+                if 0 <= j < n:
+                    f[j, q] = fp[i, q]
+                else:
+                    f[i, opp[q]] = fp[i, q]
+        u = np.array([oracle.macros(p, f[i], oracle.geq(p, T1, u[i]))[0][1:4] for i in range(n)])
+    return u
+
+
+def test_poiseuille_flow_is_exact_with_the_paper_rates():
+    """Plane Poiseuille flow under a uniform body force: with half-way bounce-
+    back walls and the paper's choice of s_q (Sec. 2.2), which pairs it with
+    the viscous rate at Lambda = 3/16, the steady lattice profile is exactly the
+    parabola F x (H - x) / (2 nu) at the nodes x = i + 1/2 (a standard exact
+    solution of two-relaxation-time schemes); a 10% change of s_q moves it
+    by ~1e-3.  Pins collision, Guo forcing with the F/2 velocity and the wall
+    position together."""
+    n, T1 = 8, 0.05
+    p = oracle.derive(n, 1e3, 0.71, oracle.SIDE_HEATED, U=0.1)
+    x = np.arange(n) + 0.5
+    exact = p.gbeta * (T1 - p.T0) / (2.0 * p.nu) * x * (n - x)
+    u = _channel(p, n, T1, 10_000)
+    assert np.abs(u[:, 2] - exact).max() < 1e-12 * exact.max()
+    assert np.abs(u[:, :2]).max() < 1e-14
+    q = oracle.derive(n, 1e3, 0.71, oracle.SIDE_HEATED, U=0.1)
+    q.s_q *= 1.1
+    uq = _channel(q, n, T1, 3_000)
+    assert np.abs(uq[:, 2] - exact).max() > 1e-4 * exact.max()
