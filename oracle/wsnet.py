@@ -5,8 +5,8 @@ parameters to its steady (u/U, v/U, w/U, T/dT) fields on an M^3 grid.
 TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``: the reference the HIP
 network kernels and their gradients are compared against.  Nothing here is
 shared with the GPU library.  The network is not part of the paper; it is the
-learned initial guess whose result the paper's steady-state criterion (Sec. 3)
-judges.  Every operation is its plain definition: zero-padded 3x3x3
+learned initial guess for runs whose convergence the paper's steady-state
+criterion (Sec. 3) decides.  Every operation is its plain definition: zero-padded 3x3x3
 cross-correlation as 27 shifted matrix products, FiLM as an affine map per
 channel, SiLU, injection and linear interpolation between grid levels, the
 mean squared error, and Adam (Kingma & Ba 2015, Algorithm 1).  Backward passes
