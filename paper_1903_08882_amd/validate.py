@@ -52,6 +52,36 @@ TABLE3 = {
 }
 
 
+def richardson(ns, fs):
+    """Order p and extrapolated value f_inf of f(h) = f_inf + C h^p, h = 1/N,
+    through three grids N1 < N2 < N3 (ratios need not be equal): p solves
+    (f1 - f2) / (f2 - f3) = (h1^p - h2^p) / (h2^p - h3^p) (by bisection on
+    [0.05, 20]), then C = (f1 - f2) / (h1^p - h2^p) and f_inf = f3 - C h3^p.
+    Returns (p, f_inf); (nan, nan) when the three values do not converge
+    monotonically."""
+    (n1, n2, n3), (f1, f2, f3) = ns, fs
+    h1, h2, h3 = 1.0 / n1, 1.0 / n2, 1.0 / n3
+    if (f1 - f2) * (f2 - f3) <= 0.0:
+        return float("nan"), float("nan")
+    target = (f1 - f2) / (f2 - f3)
+
+    def g(p):
+        return (h1 ** p - h2 ** p) / (h2 ** p - h3 ** p) - target
+
+    lo, hi = 0.05, 20.0
+    if g(lo) * g(hi) > 0.0:
+        return float("nan"), float("nan")
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(lo) * g(mid) <= 0.0:
+            hi = mid
+        else:
+            lo = mid
+    p = 0.5 * (lo + hi)
+    c = (f1 - f2) / (h1 ** p - h2 ** p)
+    return p, f3 - c * h3 ** p
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, default=129)
