@@ -42,6 +42,21 @@ def _summary(params, raw):
     return {k: nd[k] for k in KEYS}
 
 
+def standard_errors(subs, keys):
+    """Standard error of the mean of each key over equal sub-blocks: the
+    sample standard deviation of the sub-block values over sqrt(count); NaN
+    for a single sub-block."""
+    n = len(subs)
+    out = {}
+    for k in keys:
+        if n < 2:
+            out[k] = float("nan")
+            continue
+        m = sum(s[k] for s in subs) / n
+        out[k] = math.sqrt(sum((s[k] - m) ** 2 for s in subs) / (n - 1) / n)
+    return out
+
+
 def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, settle=0.01,
              max_transient_tf=400.0, avg_steps=100_000, sub=10, sample_every=100, log=print):
     opts = B.lbm_default_opts(sample_every=sample_every)
@@ -86,8 +101,7 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
     wall_avg = time.perf_counter() - ta
     mean_raw = [sum(r[j] for r in raws) / sub for j in range(len(raws[0]))]
     mean = _summary(p, mean_raw)
-    se = {k: (math.sqrt(sum((s[k] - sum(t[k] for t in subs) / sub) ** 2 for s in subs)
-                        / (sub - 1) / sub) if sub > 1 else float("nan")) for k in KEYS}
+    se = standard_errors(subs, KEYS)
     out = {"N": N, "Ra": Ra, "Pr": Pr, "storage": storage, "seed": seed,
            "steps_per_tf": tf, "transient_steps": transient, "transient_block_Nu_vol": trans,
            "avg_steps": per * sub, "avg_tf": per * sub / tf, "samples": per * sub // sample_every,

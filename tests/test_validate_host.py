@@ -1,5 +1,6 @@
-"""Host-side logic of the validation driver (no GPU): three-grid Richardson
-extrapolation, against a closed form and against the paper's own Table 2."""
+"""Host-side logic of the validation drivers (no GPU): three-grid Richardson
+extrapolation, against a closed form and against the paper's own Table 2, and
+the standard errors of the Rayleigh-Benard sub-block means."""
 import math
 
 import pytest
@@ -29,3 +30,13 @@ def test_richardson_of_the_paper_table_2():
 def test_richardson_refuses_non_monotone_values():
     p, f = richardson((81, 129, 257), [1.0, 2.0, 1.5])
     assert math.isnan(p) and math.isnan(f)
+
+
+def test_rayleigh_benard_standard_errors():
+    import numpy as np
+    from paper_1903_08882_amd.rb import standard_errors
+    rng = np.random.default_rng(3)
+    vals = rng.normal(16.0, 0.5, 10)
+    se = standard_errors([{"Nu": v} for v in vals], ["Nu"])["Nu"]
+    assert abs(se - np.std(vals, ddof=1) / np.sqrt(10)) < 1e-12
+    assert math.isnan(standard_errors([{"Nu": 1.0}], ["Nu"])["Nu"])
