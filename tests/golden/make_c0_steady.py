@@ -2,9 +2,12 @@
 side-heated configuration (33^3, Ra 1e4, Pr 0.71, U = 0.1, fluid at rest with
 the seeded +-1e-3 temperature noise), run until max|dT| over 1000 steps is
 below 1e-12 (Sec. 3's steady criterion, taken further than its 1e-8 so that
-a GPU run to the same criterion can be compared to ~1e-9).
+a GPU run to the same criterion can be compared to ~1e-9).  With --Ra 1e5 it
+writes c0_ra1e5_steady_oracle.json, the same cell at a convection-dominated
+Rayleigh number.
 
-    python tests/golden/make_c0_steady.py          (about 10-30 min, all cores)
+    python tests/golden/make_c0_steady.py            (Ra 1e4: about 2 min, all cores)
+    python tests/golden/make_c0_steady.py --Ra 1e5   (about 30 min)
 
 Uses only the oracle and the seeded input generator.
 """
@@ -19,10 +22,12 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 from paper_1903_08882_amd import synth  # noqa: E402
 
-N, RA, PR, U, TOL, CHECK, MAX_STEPS = 33, 1e4, 0.71, 0.1, 1e-12, 1000, 3_000_000
+N, PR, U, TOL, CHECK, MAX_STEPS = 33, 0.71, 0.1, 1e-12, 1000, 3_000_000
 
 
 def main():
+    RA = float(sys.argv[sys.argv.index("--Ra") + 1]) if "--Ra" in sys.argv else 1e4
+    name = "c0_steady_oracle.json" if RA == 1e4 else f"c0_ra{RA:.0e}_steady_oracle.json".replace("+0", "")
     o = oracle.Oracle(N, RA, PR, oracle.SIDE_HEATED, U=U)
     o.init_fields(synth.rest_with_noise(N, synth.SEED0))
     t0 = time.time()
@@ -44,7 +49,7 @@ def main():
                       "init": "rest + seeded noise (seed SEED0)", "tol_max_dT_per_1000": TOL},
            "steps": steps, "max_dT": float(r[0]), "rel_L1_T": float(r[1]), "rel_L2_u": float(r[2]),
            "nondimensional": {k: float(v) for k, v in nd.items()}, "residual_history": hist}
-    with open(os.path.join(HERE, "c0_steady_oracle.json"), "w") as fh:
+    with open(os.path.join(HERE, name), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out["nondimensional"]), flush=True)
 

@@ -753,3 +753,40 @@ def test_small_configuration_steady_state_matches_oracle(storage, floor, rel):
     say(f"[c0 steady {storage}] relative differences " + " ".join(f"{k} {v:+.2e}" for k, v in err.items()))
     for k in keys:
         assert abs(err[k]) <= rel * (2 if k in ("E", "eps_u", "eps_T") else 1), (k, nd[k], no[k], err[k])
+
+
+C0_RA1E5_STEADY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c0_ra1e5_steady_oracle.json")
+
+
+@pytest.mark.parametrize("storage,floor,rel", [("fp64", 1e-12, 1e-9), ("fp32", 1e-6, 2e-4)])
+def test_small_cell_at_ra_1e5_steady_state_matches_oracle(storage, floor, rel):
+    """The 33^3 cell at Ra 1e5 (convection-dominated: thin boundary layers,
+    Re ~ 40) run to steady state against the oracle's own steady state
+    (tests/golden/c0_ra1e5_steady_oracle.json, make_c0_steady.py --Ra 1e5).
+    FP64 to the oracle's criterion (max |dT| < 1e-12 over 1000 steps) and to
+    1e-9 in every number; FP32 for the oracle's step count plus 10 000 steps,
+    steady to its floor, and to 2e-4 (4e-4 for the quadratic numbers)."""
+    if not os.path.exists(C0_RA1E5_STEADY):
+        pytest.skip("the stored oracle steady state is not written yet (make_c0_steady.py --Ra 1e5)")
+    ref = json.load(open(C0_RA1E5_STEADY))
+    cfg = ref["config"]
+    h = B.lbm_create(cfg["N"], cfg["Ra"], cfg["Pr"], "side_heated", storage, B.lbm_default_opts(U=cfg["U"]))
+    B.lbm_set_fields(h, dev(synth.rest_with_noise(cfg["N"], synth.SEED0)))
+    if storage == "fp64":
+        steps, res, _ = B.lbm_run_to_steady(h, 1000, cfg["tol_max_dT_per_1000"], 3 * ref["steps"])
+    else:
+        steps = ref["steps"] + 10_000
+        B.lbm_step(h, steps - 1000)
+        B.lbm_residual(h)
+        B.lbm_step(h, 1000)
+        res = B.lbm_residual(h)[0]
+    nd = B.lbm_nondimensional(B.lbm_get_params(h), B.lbm_observables_raw(h))
+    no = ref["nondimensional"]
+    say(f"[Ra 1e5 steady {storage}] {steps} steps, max|dT| {res:.2e} (oracle {ref['steps']} steps)")
+    assert res < floor
+    keys = ("Nu_hot", "Nu_cold", "Nu_hot_mid", "Nu_hot_fd", "Nu_hot_mid_fd", "Re_rms", "Re_w",
+            "eps_u", "eps_T", "Nu_vol", "E")
+    err = {k: (nd[k] - no[k]) / abs(no[k]) for k in keys}
+    say(f"[Ra 1e5 steady {storage}] relative differences " + " ".join(f"{k} {v:+.2e}" for k, v in err.items()))
+    for k in keys:
+        assert abs(err[k]) <= rel * (2 if k in ("E", "eps_u", "eps_T") else 1), (k, nd[k], no[k], err[k])

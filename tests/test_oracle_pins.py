@@ -577,14 +577,15 @@ def test_midline_flux_weighting_for_odd_and_even_N(cell, N):
         assert abs(r[mid] - r[whole]) <= tol * abs(r[whole]), (whole, r[whole], r[mid])
 
 
-def test_stored_c0_steady_state_is_steady_and_balanced():
-    """The stored oracle steady state of the small configuration
-    (golden/c0_steady_oracle.json): it met its criterion, the heat entering at
+@pytest.mark.parametrize("name", ["c0_steady_oracle.json", "c0_ra1e5_steady_oracle.json"])
+def test_stored_c0_steady_state_is_steady_and_balanced(name):
+    """The stored oracle steady states of the small cell (Ra 1e4 and 1e5,
+    golden/c0_*steady_oracle.json): each met its criterion, the heat entering at
     the hot wall leaves at the cold wall (link-flux Nu equal to 1e-9, an exact
     balance at a steady state), the mid-line Nu exceeds the wall average as in
     every row of Tables 1-2, and the mean temperature stays at the walls' mean."""
     import json
-    d = json.load(open(os.path.join(GOLDEN, "c0_steady_oracle.json")))
+    d = json.load(open(os.path.join(GOLDEN, name)))
     nd = d["nondimensional"]
     assert d["max_dT"] < d["config"]["tol_max_dT_per_1000"]
     assert abs(nd["Nu_hot"] - nd["Nu_cold"]) < 1e-9 * nd["Nu_hot"]
