@@ -129,8 +129,10 @@ typedef struct {
     double T0;        /* reference temperature of the buoyancy; default 0    */
     int sample_every; /* lbm_step adds the observables to the time averages
                          every this many steps (0 = never; default 0)          */
-    int block;        /* threads per block of the step kernel, a multiple of
-                         64 in [64, 1024]; 0 = library default                */
+    int block;        /* threads per block of the step kernel: 64, 128, 192
+                         or 256 (the step kernels are compiled for at most
+                         256 threads per block); 0 = library default (256);
+                         anything else gives LBM_EINVAL from lbm_create      */
     int waves_even;   /* occupancy cap of the step kernel, waves per SIMD, for
                          even and odd steps: 1..8, 0 = library default for the
                          storage type (FP32: 2 and 3; FP16S: 3 and none; FP16C:

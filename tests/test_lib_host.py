@@ -120,6 +120,25 @@ def test_create_rejects_bad_buffers_without_touching_the_gpu():
     assert lib.lbm_strerror(-5) == b"non-finite result (diverged)"
 
 
+def test_create_accepts_exactly_the_documented_block_sizes():
+    """lbm.h documents opts.block as 64, 128, 192 or 256 (0 = default): those
+    create a handle (a fake, never dereferenced device address is enough, as
+    lbm_create touches no device memory) and every other value is rejected."""
+    import ctypes
+    lib = B.lib()
+    for block in (0, 64, 128, 192, 256, -64, 1, 32, 96, 255, 320, 512, 1024):
+        o = B.lbm_default_opts(U=0.1)
+        o.block = block
+        h = ctypes.c_void_p()
+        rc = lib.lbm_create(33, 1e4, 0.71, 0, 1, ctypes.byref(o), ctypes.c_void_p(0x100000),
+                            1 << 30, ctypes.byref(h))
+        if block in (0, 64, 128, 192, 256):
+            assert rc == 0 and h.value, block
+            assert lib.lbm_destroy(h) == 0
+        else:
+            assert rc == -1 and not h.value, block
+
+
 def test_warm_start_symbols_exported_and_bound():
     from paper_1903_08882_amd import lws
     text = open(os.path.join(ROOT, "include", "lws.h")).read()
