@@ -50,6 +50,7 @@ def lib():
         L.orc_macro_fields.argtypes = [pp, dp, dp]
         L.orc_observables.argtypes = [pp, dp, dp, dp]
         L.orc_residual.argtypes = [pp, dp, dp, dp]
+        L.orc_nusselt_profile.argtypes = [pp, dp, dp]
         L.orc_collide.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_macros.argtypes = [pp, dp, dp, dp, dp]
         L.orc_feq.argtypes = [ctypes.c_double, dp, dp]
@@ -252,6 +253,14 @@ class Oracle:
         r = np.zeros(NRAW)
         lib().orc_observables(ctypes.byref(self.p), _dp(m), _dp(self.flux), _dp(r))
         return r
+
+    def nusselt_profile(self, macro=None):
+        """Plane-averaged Nu on the N node planes across the cell (x for the
+        side-heated cell, z for Rayleigh-Benard), oracle.c orc_nusselt_profile."""
+        m = self.macro() if macro is None else _f64(macro)
+        out = np.zeros(self.N)
+        lib().orc_nusselt_profile(ctypes.byref(self.p), _dp(m), _dp(out))
+        return out
 
     def residual(self, macro_old, macro=None):
         m = self.macro() if macro is None else _f64(macro)

@@ -713,6 +713,39 @@ void orc_observables(const orc_params *p, const double *macro, const double *flu
 }
 
 /*
+ * Plane-averaged Nusselt number across the cell (Sec. 3, the Nu(y) of its
+ * Fig. 4, which runs from the hot to the cold wall; here along x for the
+ * side-heated cell and along z for Rayleigh-Benard): on node plane k of that
+ * axis a,
+ *   out[k] = H/(kappa dT) * ( <u_a T>_k - kappa <d_a T>_k ),
+ * the convective plus the conductive heat flux through the plane in units of
+ * the conduction flux kappa dT/H, means over the plane's N^2 nodes, d_a T
+ * from orc_fd_derivative (central inside; at the first node next to a wall
+ * the quadratic through the wall temperature).
+ */
+void orc_nusselt_profile(const orc_params *p, const double *macro, double *out) {
+    int N = p->N;
+    size_t V = (size_t)N * N * N;
+    int axis = p->cell == 0 ? 0 : 2;
+    const double *ua = macro + (size_t)(1 + axis) * V, *T = macro + 4 * V;
+    double *conv = (double *)calloc((size_t)N, sizeof(double));
+    double *cond = (double *)calloc((size_t)N, sizeof(double));
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                int c[3] = {x, y, z};
+                size_t n = nid(N, x, y, z);
+                conv[c[axis]] += ua[n] * T[n];
+                cond[c[axis]] += orc_fd_derivative(N, T, axis, c, p->T_hot, p->T_cold, 0, 0);
+            }
+    double A = (double)N * N;
+    for (int k = 0; k < N; ++k)
+        out[k] = p->H / (p->kappa * p->dT) * (conv[k] / A - p->kappa * cond[k] / A);
+    free(conv);
+    free(cond);
+}
+
+/*
  * Steady-state residual between two macro states (Sec. 3 criterion):
  *   res[0] = max |T - T_old|
  *   res[1] = sum |T - T_old| / sum |T_old|            (relative L1 of T)

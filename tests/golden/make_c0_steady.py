@@ -1,15 +1,23 @@
-"""Writes c0_steady_oracle.json: the FP64 oracle's steady state of the small
-side-heated configuration (33^3, Ra 1e4, Pr 0.71, U = 0.1, fluid at rest with
-the seeded +-1e-3 temperature noise), run until max|dT| over 1000 steps is
-below 1e-12 (Sec. 3's steady criterion, taken further than its 1e-8 so that
-a GPU run to the same criterion can be compared to ~1e-9).  With --Ra 1e5 it
-writes c0_ra1e5_steady_oracle.json, the same cell at a convection-dominated
-Rayleigh number.
+"""Writes the stored oracle steady states the tests compare against, each run
+from the seeded start until max|dT| over 1000 steps is below 1e-12 (Sec. 3's
+steady criterion, taken further than its 1e-8 so that a GPU run to the same
+criterion can be compared to ~1e-9):
 
-    python tests/golden/make_c0_steady.py            (Ra 1e4: about 2 min, all cores)
-    python tests/golden/make_c0_steady.py --Ra 1e5   (about 30 min)
+    python tests/golden/make_c0_steady.py
+        c0_steady_oracle.json: the small side-heated configuration (33^3,
+        Ra 1e4, Pr 0.71, U = 0.1, fluid at rest with the seeded +-1e-3
+        temperature noise); about 2 min on all cores
+    python tests/golden/make_c0_steady.py --Ra 1e5
+        c0_ra1e5_steady_oracle.json: the same cell at a convection-dominated
+        Rayleigh number; about 30 min
+    python tests/golden/make_c0_steady.py --cell rb --N 17 --Ra 1e4 --tol 1e-11
+        rb17_ra1e4_steady_oracle.json: the Rayleigh-Benard cube (Sec. 4) above
+        onset, a single steady roll; a few minutes (its residual levels off
+        near 2e-12, so it stops at 1e-11)
 
-Uses only the oracle and the seeded input generator.
+Each file holds the nondimensional numbers, the raw FP64 vector they come
+from and the plane-averaged Nusselt profile across the cell.  Uses only the
+oracle and the seeded input generator.
 """
 import json
 import os
@@ -22,13 +30,24 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 from paper_1903_08882_amd import synth  # noqa: E402
 
-N, PR, U, TOL, CHECK, MAX_STEPS = 33, 0.71, 0.1, 1e-12, 1000, 3_000_000
+PR, U, TOL, CHECK, MAX_STEPS = 0.71, 0.1, 1e-12, 1000, 3_000_000
+
+
+def arg(name, default):
+    return sys.argv[sys.argv.index(name) + 1] if name in sys.argv else default
 
 
 def main():
-    RA = float(sys.argv[sys.argv.index("--Ra") + 1]) if "--Ra" in sys.argv else 1e4
-    name = "c0_steady_oracle.json" if RA == 1e4 else f"c0_ra{RA:.0e}_steady_oracle.json".replace("+0", "")
-    o = oracle.Oracle(N, RA, PR, oracle.SIDE_HEATED, U=U)
+    RA = float(arg("--Ra", "1e4"))
+    tol = float(arg("--tol", str(TOL)))
+    N = int(arg("--N", "33"))
+    cell = arg("--cell", "side_heated")
+    if cell == "side_heated" and N == 33:
+        name = "c0_steady_oracle.json" if RA == 1e4 else f"c0_ra{RA:.0e}_steady_oracle.json".replace("+0", "")
+    else:
+        name = f"{'rb' if cell == 'rb' else 'sh'}{N}_ra{RA:.0e}_steady_oracle.json".replace("+0", "")
+    o = oracle.Oracle(N, RA, PR, oracle.SIDE_HEATED if cell == "side_heated" else oracle.RAYLEIGH_BENARD,
+                      U=U)
     o.init_fields(synth.rest_with_noise(N, synth.SEED0))
     t0 = time.time()
     m = o.macro()
@@ -42,13 +61,17 @@ def main():
         if steps % 20000 == 0:
             hist.append([steps, float(r[0])])
             print(f"{steps} steps  max|dT| {r[0]:.3e}  {time.time() - t0:.0f} s", flush=True)
-        if r[0] < TOL:
+        if r[0] < tol:
             break
-    nd = oracle.nondimensional(o.p, o.observables_raw())
-    out = {"config": {"N": N, "Ra": RA, "Pr": PR, "U": U, "cell": "side_heated",
-                      "init": "rest + seeded noise (seed SEED0)", "tol_max_dT_per_1000": TOL},
+    raw = o.observables_raw()
+    nd = oracle.nondimensional(o.p, raw)
+    out = {"config": {"N": N, "Ra": RA, "Pr": PR, "U": U,
+                      "cell": "side_heated" if cell == "side_heated" else "rayleigh_benard",
+                      "init": "rest + seeded noise (seed SEED0)", "tol_max_dT_per_1000": tol},
            "steps": steps, "max_dT": float(r[0]), "rel_L1_T": float(r[1]), "rel_L2_u": float(r[2]),
-           "nondimensional": {k: float(v) for k, v in nd.items()}, "residual_history": hist}
+           "nondimensional": {k: float(v) for k, v in nd.items()},
+           "raw": [float(v) for v in raw],
+           "nusselt_profile": [float(v) for v in o.nusselt_profile()], "residual_history": hist}
     with open(os.path.join(HERE, name), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out["nondimensional"]), flush=True)

@@ -577,20 +577,118 @@ def test_midline_flux_weighting_for_odd_and_even_N(cell, N):
         assert abs(r[mid] - r[whole]) <= tol * abs(r[whole]), (whole, r[whole], r[mid])
 
 
-@pytest.mark.parametrize("name", ["c0_steady_oracle.json", "c0_ra1e5_steady_oracle.json"])
-def test_stored_c0_steady_state_is_steady_and_balanced(name):
-    """The stored oracle steady states of the small cell (Ra 1e4 and 1e5,
-    golden/c0_*steady_oracle.json): each met its criterion, the heat entering at
-    the hot wall leaves at the cold wall (link-flux Nu equal to 1e-9, an exact
-    balance at a steady state), the mid-line Nu exceeds the wall average as in
-    every row of Tables 1-2, and the mean temperature stays at the walls' mean."""
+STEADY = ["c0_steady_oracle.json", "c0_ra1e5_steady_oracle.json", "rb17_ra1e4_steady_oracle.json"]
+
+
+def _steady(name):
     import json
     d = json.load(open(os.path.join(GOLDEN, name)))
+    c = d["config"]
+    cell = oracle.SIDE_HEATED if c["cell"] == "side_heated" else oracle.RAYLEIGH_BENARD
+    p = oracle.derive(c["N"], c["Ra"], c["Pr"], cell, c["U"])
+    return d, p, np.array(d["raw"])
+
+
+@pytest.mark.parametrize("name", STEADY)
+def test_stored_steady_state_is_steady_and_balanced(name):
+    """The stored oracle steady states (golden/*_steady_oracle.json: the small
+    side-heated cell at Ra 1e4 and 1e5, the Rayleigh-Benard cube at Ra 1e4,
+    written by golden/make_c0_steady.py): each met its criterion, its stored
+    numbers are the conversion of its stored raw vector, the heat entering at
+    the hot wall leaves at the cold wall (link-flux Nu equal to 1e-9 for the
+    side-heated cell; the Rayleigh-Benard cube keeps the undamped space-time
+    checkerboard of w, so its two walls differ by a few 1e-6 from step to
+    step), the mid-line Nu exceeds the wall average as in every row of
+    Tables 1-2, and the mean temperature stays at the walls' mean."""
+    d, p, raw = _steady(name)
     nd = d["nondimensional"]
     assert d["max_dT"] < d["config"]["tol_max_dT_per_1000"]
-    assert abs(nd["Nu_hot"] - nd["Nu_cold"]) < 1e-9 * nd["Nu_hot"]
+    for k, v in oracle.nondimensional(p, raw).items():
+        assert v == nd[k], k
+    tol = 1e-9 if p.cell == oracle.SIDE_HEATED else 2e-5
+    assert abs(nd["Nu_hot"] - nd["Nu_cold"]) < tol * nd["Nu_hot"]
     assert nd["Nu_hot_mid"] > nd["Nu_hot"] > 1.0
     assert abs(nd["mean_T"]) < 1e-9
+
+
+def _pins(p, raw, nd):
+    """The balances a steady state of the closed cell must satisfy (Sec. 3, 4),
+    each as a relative misfit; see test_nondimensional_scalings_pinned_by_steady_balances."""
+    U, dT = p.U, p.dT
+    wT = raw[10] / (U * dT)                                   # <w* T*>
+    m = {"vol_vs_walls": nd["Nu_vol"] / (0.5 * (nd["Nu_hot"] + nd["Nu_cold"])) - 1.0,
+         "th_vs_wall": nd["Nu_th"] / nd["Nu_hot"] - 1.0,
+         "eps_u_vs_buoyancy": nd["eps_u"] / wT - 1.0,
+         "Re_vs_E": nd["Re_rms"] ** 2 / (2.0 * nd["E"] * p.Ra / p.Pr) - 1.0,
+         "Re_w_vs_Re": (nd["Re_w"] / nd["Re_rms"]) ** 2 / (raw[9] / raw[8]) - 1.0}
+    s = np.sqrt(p.Ra * p.Pr)
+    m["kin_vs_buoyancy"] = (nd["Nu_kin"] - 1.0) / (s * wT) - 1.0
+    return m
+
+
+# Bounds of the misfits: the exact identities at rounding level; the
+# dissipation balances carry the truncation error of the gradient estimator,
+# measured 0.5-1.8% (thermal) and 1.8-7.4% (viscous: 7.4% in the thin
+# boundary layers of the 33^3 cell at Ra 1e5, Re ~ 40) at N = 17 and 33
+# (the paper's own Table 4 spread on finer grids is up to 1.06%).  Every
+# planted slip is a factor of 2 or more.
+PIN_TOL = {"vol_vs_walls": 1e-9, "th_vs_wall": 0.03, "eps_u_vs_buoyancy": 0.10, "Re_vs_E": 1e-12,
+           "Re_w_vs_Re": 1e-12, "kin_vs_buoyancy": 0.10}
+
+
+def _mutants(p, raw):
+    """Conversions with one plausible slip each (planted here, in a copy of
+    the oracle's conversion, on the CPU)."""
+    good = oracle.nondimensional(p, raw)
+    H, U, s = p.H, p.U, np.sqrt(p.Ra * p.Pr)
+    out = {}
+
+    def mut(name, **kw):
+        d = dict(good)
+        d.update(kw)
+        out[name] = d
+
+    eu, eT = good["eps_u"], good["eps_T"]
+    mut("eps_u with U^2 for U^3", eps_u=raw[12] * H / U ** 2, Nu_kin=1 + s * raw[12] * H / U ** 2)
+    mut("eps_u without H", eps_u=raw[12] / U ** 3, Nu_kin=1 + s * raw[12] / U ** 3)
+    mut("eps_u doubled (nu for nu/2)", eps_u=2 * eu, Nu_kin=1 + 2 * s * eu)
+    mut("Nu_kin without sqrt(Ra Pr)", Nu_kin=1 + eu)
+    mut("Nu_th without sqrt(Ra Pr)", Nu_th=eT)
+    mut("Nu_th with Ra for sqrt(Ra Pr)", Nu_th=p.Ra * eT)
+    mut("eps_T halved", eps_T=0.5 * eT, Nu_th=0.5 * s * eT)
+    mut("eps_T with U^3", eps_T=raw[13] * H / U ** 3, Nu_th=s * raw[13] * H / U ** 3)
+    mut("E without 1/2", E=raw[8] / U ** 2)
+    mut("Re without sqrt", Re_rms=raw[8] * H / p.nu)
+    mut("Re with kappa for nu", Re_rms=np.sqrt(raw[8]) * H / p.kappa)
+    mut("Re_w from <|u|^2>", Re_w=good["Re_rms"])
+    mut("Re_w without sqrt", Re_w=raw[9] * H / p.nu)
+    mut("Nu_vol with <u T> and <w T> swapped",
+        Nu_vol=1 + s * (raw[11] if p.cell == oracle.RAYLEIGH_BENARD else raw[10]) / (U * p.dT))
+    mut("Nu_vol without sqrt(Ra Pr)",
+        Nu_vol=1 + (raw[10] if p.cell == oracle.RAYLEIGH_BENARD else raw[11]) / (U * p.dT))
+    return out
+
+
+@pytest.mark.parametrize("name", STEADY)
+def test_nondimensional_scalings_pinned_by_steady_balances(name):
+    """At a steady state of the closed cell the nondimensional numbers of
+    Sec. 3-4 are tied together by balances the conversion must reproduce:
+    the volume heat flux equals the walls' (Nu_vol, exact on the lattice up to
+    rounding); the thermal dissipation carries the same heat
+    (Nu_th = Nu, Sec. 4); the viscous dissipation equals the buoyancy power,
+    eps_u* = <w* T*>, so Nu_kin - 1 = sqrt(Ra Pr) <w* T*> (in the
+    Rayleigh-Benard cube that is Nu_kin = Nu_vol, Sec. 4);
+    Re_rms^2 = 2 E Ra/Pr (Re = sqrt<|u|^2> H/nu, E = <|u*|^2>/2); Re_w^2/Re^2 =
+    <w^2>/<|u|^2>.  The oracle's conversion meets all of them; every planted
+    slip of a factor, a power or a square root breaks at least one."""
+    d, p, raw = _steady(name)
+    nd = oracle.nondimensional(p, raw)
+    misfit = _pins(p, raw, nd)
+    for k, v in misfit.items():
+        assert abs(v) < PIN_TOL[k], (k, v)
+    for what, bad in _mutants(p, raw).items():
+        m = _pins(p, raw, bad)
+        assert any(abs(v) >= PIN_TOL[k] for k, v in m.items()), what
 
 
 def _channel(p, n, T1, steps):
@@ -634,3 +732,114 @@ def test_poiseuille_flow_is_exact_with_the_paper_rates():
     q.s_q *= 1.1
     uq = _channel(q, n, T1, 3_000)
     assert np.abs(uq[:, 2] - exact).max() > 1e-4 * exact.max()
+
+
+def test_velocity_components_and_heat_flux_products_of_a_uniform_state():
+    """A uniform state (u, v, w, T) = (a, b, c, d) with a, b, c distinct makes
+    every volume mean a known product: <|u|^2> = a^2 + b^2 + c^2, <w^2> = c^2,
+    <w T> = c d, <u T> = a d, <T> = d, <rho - 1> = r.  Any mix-up of the
+    velocity components (w read as u, say) or of the two heat-flux products
+    changes one of them.  The gradients of a uniform field vanish inside; the
+    walls (u = 0, T = +-1/2) then enter only at the nodes next to them, which
+    is checked on eps_u against its closed form for a constant profile."""
+    N = 6
+    o = oracle.Oracle(N, 1e4, 0.71, oracle.RAYLEIGH_BENARD, U=0.1)
+    a, b, c, d, r = 0.011, -0.023, 0.037, 0.13, 2e-4
+    macro = np.empty((5, N ** 3))
+    macro[:] = np.array([1.0 + r, a, b, c, d])[:, None]
+    raw = o.observables_raw(macro)
+    assert abs(raw[8] - (a * a + b * b + c * c)) < 1e-17
+    assert abs(raw[9] - c * c) < 1e-17
+    assert abs(raw[10] - c * d) < 1e-17
+    assert abs(raw[11] - a * d) < 1e-17
+    assert abs(raw[15] - d) < 1e-16
+    assert abs(raw[16] - r) < 1e-16 and abs(raw[14] - r * r) < 1e-19
+    # eps_u: inside, every difference of a uniform field vanishes; at the node
+    # next to a wall along axis i the quadratic through the wall value 0 gives
+    # d_i u_j = +-(4/3) u_j (+ at the low wall, - at the high one).  The cross
+    # products d_i u_j d_j u_i (i != j) live on the edges, where the four sign
+    # combinations cancel, so <(d_i u_j + d_j u_i)^2> = f (4/3)^2 (u_j^2 + u_i^2)
+    # for i != j and 4 f (4/3)^2 u_i^2 for i = j, f = 2/N the share of nodes
+    # next to one of the two walls of an axis.
+    f, g2, comps = 2.0 / N, (4.0 / 3.0) ** 2, (a, b, c)
+    s2 = sum(f * g2 * (comps[j] ** 2 + comps[i] ** 2) if i != j else 4 * f * g2 * comps[i] ** 2
+             for i in range(3) for j in range(3))
+    assert abs(raw[12] - 0.5 * o.p.nu * s2) < 1e-15 * max(1.0, raw[12])
+
+
+def test_residual_sums_per_node_norms_of_the_velocity_change():
+    """The velocity residual of Sec. 3 is sum_n ||u_n - u_n^old||_2 over
+    sum_n ||u_n^old||_2, a sum of per-node Euclidean norms, not the ratio of two
+    global L2 norms.  Old state u = (1, 0, 0) at every one of the 27 nodes;
+    the change is (3, 4, 0) at one node and (0, 0, 12) at another: the paper's
+    measure gives (5 + 12)/27, a global L2 norm would give 13/sqrt(27) (and a
+    sum of squares 169/27).  The temperature part: max and relative L1 of a
+    change of +0.2 at one node and -0.5 at another on T_old = 0.1."""
+    N = 3
+    o = oracle.Oracle(N, 1e4, 0.71, oracle.SIDE_HEATED, U=0.1)
+    old = np.zeros((5, 27))
+    old[0] = 1.0
+    old[1] = 1.0
+    old[4] = 0.1
+    new = old.copy()
+    new[1:4, 4] += np.array([3.0, 4.0, 0.0])
+    new[1:4, 20] += np.array([0.0, 0.0, 12.0])
+    new[4, 7] += 0.2
+    new[4, 11] -= 0.5
+    res = o.residual(old, new)
+    assert abs(res[2] - 17.0 / 27.0) < 1e-15
+    assert abs(res[2] - 13.0 / np.sqrt(27.0)) > 1.0
+    assert abs(res[0] - 0.5) < 1e-15
+    assert abs(res[1] - 0.7 / 2.7) < 1e-15
+
+
+@pytest.mark.parametrize("cell", [oracle.SIDE_HEATED, oracle.RAYLEIGH_BENARD])
+def test_nusselt_profile_of_conduction_and_of_a_quadratic_state(cell):
+    """Plane-averaged Nu across the cell (Sec. 3, Fig. 4's Nu(y)).  Linear
+    conduction between the isothermal walls (no flow) carries exactly the
+    conduction flux through every plane: Nu(k) = 1.  A temperature quadratic
+    along the axis, T = T_h - dT s/H + c s (H - s) at the node positions
+    s = k + 1/2, with a uniform velocity a along that axis, has
+    Nu(k) = H/(kappa dT) (a T(s) - kappa T'(s)), T'(s) = -dT/H + c (H - 2 s):
+    the wall rows use the quadratic through the wall temperature, exact here.
+    A sign slip (heat counted towards the hot wall), the other velocity
+    component or a plane mean over the wrong axis misses both."""
+    N = 9
+    o = oracle.Oracle(N, 1e4, 0.71, cell, U=0.1)
+    p = o.p
+    axis = 0 if cell == oracle.SIDE_HEATED else 2
+    s = np.arange(N) + 0.5
+    shape = [1, 1, 1]
+    shape[2 - axis] = N
+    macro = np.zeros((5, N, N, N))
+    macro[0] = 1.0
+    macro[4] = np.broadcast_to((p.T_hot - p.dT * s / N).reshape(shape), (N, N, N))
+    assert np.abs(o.nusselt_profile(macro.reshape(5, -1)) - 1.0).max() < 1e-13
+    c, a = 0.004, 0.013
+    Ts = p.T_hot - p.dT * s / N + c * s * (N - s)
+    dTs = -p.dT / N + c * (N - 2 * s)
+    macro[4] = np.broadcast_to(Ts.reshape(shape), (N, N, N))
+    macro[1 + axis] = a
+    want = N / (p.kappa * p.dT) * (a * Ts - p.kappa * dTs)
+    got = o.nusselt_profile(macro.reshape(5, -1))
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # the velocity across the planes matters, the others do not
+    macro[1 + axis] = 0.0
+    macro[1 + (axis + 1) % 3] = a
+    assert np.abs(o.nusselt_profile(macro.reshape(5, -1)) - want).max() > 0.1
+
+
+@pytest.mark.parametrize("name", STEADY)
+def test_stored_steady_nusselt_profile_is_flat(name):
+    """In a steady state no heat piles up between two planes, so the profile
+    across the cell is flat and equal to the wall Nusselt number, up to the
+    truncation error of the differences: within 3% of the mean wall Nu at
+    every plane at N = 17 and 33 in the stored oracle steady states (measured
+    0.8-2.6%, the most at Ra 1e5), its mean within 0.1% (measured
+    0.007-0.05%)."""
+    d, p, raw = _steady(name)
+    prof = np.array(d["nusselt_profile"])
+    nu = 0.5 * (d["nondimensional"]["Nu_hot"] + d["nondimensional"]["Nu_cold"])
+    assert prof.shape == (p.N,)
+    assert np.abs(prof / nu - 1.0).max() < 0.03, prof / nu
+    assert abs(prof.mean() / nu - 1.0) < 0.001
