@@ -274,6 +274,21 @@ LBM_API int lbm_run_to_steady(lbm_t *h, int64_t check_every, double tol_max_dT,
  * lines are averaged.  Synchronises stream. */
 LBM_API int lbm_centerline_peaks(lbm_t *h, void *stream, double out[5]);
 
+/* Plane-averaged Nusselt number across the cell (Sec. 3: the Nu(y) profile
+ * of its Fig. 4, from the hot to the cold wall; here along x for the
+ * side-heated cell and along z for Rayleigh-Benard).  out[k], k = 0..N-1, is
+ * the heat carried through the node plane at (k + 1/2)/N of that axis a, by
+ * convection and conduction, in units of the conduction flux kappa dT/H:
+ *   Nu(k) = H/(kappa dT) (<u_a T>_k - kappa <d_a T>_k),
+ * means over the plane's N^2 nodes, d_a T with the differences of the
+ * observables (central inside; at the first node next to a wall the
+ * quadratic through the wall temperature).  Linear conduction gives 1 on
+ * every plane; in a steady state every plane carries the same heat, so the
+ * profile is flat up to the differences' truncation error.  out: host array
+ * of N doubles.  Synchronises stream; LBM_EDIVERGED when a value is not
+ * finite. */
+LBM_API int lbm_nusselt_profile(lbm_t *h, void *stream, double *out);
+
 /* Fields (u, v, w, T) trilinearly resampled onto M^3 node-centred points
  * (i + 1/2)/M, FP32 [4][M^3] in device memory.  Per axis the samples are the
  * nodes and, beyond the outermost nodes, the walls: u = v = w = 0 on all
@@ -324,6 +339,14 @@ LBM_API int lbm_batch_autotune(lbm_batch_t *b, void *stream, int steps_per_candi
                                int *best_block, double *best_ms);
 
 LBM_API const char *lbm_batch_last_error(const lbm_batch_t *b);
+
+/* Reference device copy for measuring the practical HBM bandwidth that the
+ * step kernels are compared against (not part of the method): copies bytes
+ * from src to dst, both device memory, with 16-byte streaming loads and
+ * stores on stream (asynchronous).  bytes must be a multiple of 16 and both
+ * pointers 16-byte aligned; the ranges must not overlap (LBM_EINVAL
+ * otherwise); LBM_EDEVICE when the launch fails. */
+LBM_API int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Kernel timing.  With profiling enabled, lbm_step brackets every step
  * kernel it launches with a pair of HIP events on its stream.

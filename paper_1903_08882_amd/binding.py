@@ -79,6 +79,8 @@ _SIG = {
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int64, _P]),
     "lbm_time": (ctypes.c_int64, [_P]),
     "lbm_observables_raw": (ctypes.c_int, [_P, _P, _D]),
+    "lbm_nusselt_profile": (ctypes.c_int, [_P, _P, _D]),
+    "lbm_device_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lbm_observables": (ctypes.c_int, [_P, _P, _D, _D, _D, _D]),
     "lbm_nondimensional": (ctypes.c_int, [ctypes.POINTER(lbm_params), _D, _D]),
     "lbm_averages": (ctypes.c_int, [_P, _P, _D, ctypes.POINTER(ctypes.c_int64)]),
@@ -249,6 +251,23 @@ def lbm_observables_raw(h, stream=None):
     raw = (ctypes.c_double * NRAW)()
     _check(lib().lbm_observables_raw(h.ptr, _stream(stream), raw), h.ptr)
     return list(raw)
+
+
+def lbm_device_copy(dst, src, stream=None):
+    """Reference streaming copy of the CUDA tensor src into dst (same byte
+    size, a multiple of 16), asynchronous on stream."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise LBMError(-1, "lbm_device_copy needs two CUDA tensors of the same byte size")
+    _check(lib().lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream(stream)))
+
+
+def lbm_nusselt_profile(h, stream=None):
+    """Plane-averaged Nu on the N node planes across the cell (list of N)."""
+    n = lbm_get_params(h).N
+    out = (ctypes.c_double * n)()
+    _check(lib().lbm_nusselt_profile(h.ptr, _stream(stream), out), h.ptr)
+    return list(out)
 
 
 def lbm_observables(h, stream=None):

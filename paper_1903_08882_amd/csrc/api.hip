@@ -47,6 +47,17 @@ int require_init(lbm_t *h) {
     return LBM_OK;
 }
 
+// Take the pending sample of the current state (see lbm_step) into the time
+// averages now, with a separate pass over the populations.
+int flush_sample(lbm_t *h, hipStream_t s) {
+    if (!h->pending_sample) return LBM_OK;
+    hipError_t e = lbmk::launch_observe(h, true, s);
+    if (e != hipSuccess) return hip_fail(h, e, "observables");
+    h->samples += 1;
+    h->pending_sample = false;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -188,6 +199,7 @@ int lbm_set_fields(lbm_t *h, const double *uvwT, void *stream) {
     h->parity = 0;
     h->t = 0;
     h->has_flux = false;
+    h->pending_sample = false;
     h->initialised = true;
     if ((e = lbmk::launch_reset_acc(h, s)) != hipSuccess) return hip_fail(h, e, "reset averages");
     h->samples = 0;
@@ -199,7 +211,7 @@ int lbm_get_fields(lbm_t *h, double *out, void *stream) {
     int rc = require_init(h);
     if (rc) return rc;
     if (!out) return fail(h, LBM_EINVAL, "out is NULL");
-    hipError_t e = lbmk::launch_macro(h, out, nullptr, as_stream(stream));
+    hipError_t e = lbmk::launch_macro(h, out, as_stream(stream));
     return e == hipSuccess ? LBM_OK : hip_fail(h, e, "macro kernel");
 }
 
@@ -211,6 +223,7 @@ int lbm_set_populations(lbm_t *h, const double *in, void *stream) {
     if (e != hipSuccess) return hip_fail(h, e, "set populations");
     h->parity = 0;
     h->has_flux = false;
+    h->pending_sample = false;
     h->initialised = true;
     if ((e = lbmk::launch_reset_acc(h, s)) != hipSuccess) return hip_fail(h, e, "reset averages");
     h->samples = 0;
@@ -245,19 +258,24 @@ int lbm_step(lbm_t *h, int64_t n, void *stream) {
             if ((e = hipEventRecord(h->events[h->events_used], s)) != hipSuccess)
                 return hip_fail(h, e, "event record");
         }
-        if ((e = lbmk::launch_step(h, h->parity, s)) != hipSuccess) return hip_fail(h, e, "step kernel");
+        // a sample state left by the previous step is observed by the step
+        // that leaves it, from the populations it loads anyway
+        const bool obs = h->pending_sample;
+        if ((e = lbmk::launch_step(h, h->parity, obs, s)) != hipSuccess) return hip_fail(h, e, "step kernel");
         if (h->profiling) {
             if ((e = hipEventRecord(h->events[h->events_used + 1], s)) != hipSuccess)
                 return hip_fail(h, e, "event record");
             h->events_used += 2;
         }
+        if (obs) {
+            if ((e = lbmk::launch_observe_reduce(h, true, s)) != hipSuccess) return hip_fail(h, e, "observables");
+            h->samples += 1;
+            h->pending_sample = false;
+        }
         h->parity ^= 1;
         h->t += 1;
         h->has_flux = true;
-        if (h->o.sample_every > 0 && h->t % h->o.sample_every == 0) {
-            if ((e = lbmk::launch_observe(h, true, s)) != hipSuccess) return hip_fail(h, e, "observables");
-            h->samples += 1;
-        }
+        if (h->o.sample_every > 0 && h->t % h->o.sample_every == 0) h->pending_sample = true;
     }
     return LBM_OK;
 }
@@ -320,6 +338,7 @@ int lbm_averages(lbm_t *h, void *stream, double raw_mean[LBM_NRAW], int64_t *cou
     int rc = require_init(h);
     if (rc) return rc;
     if (!raw_mean) return fail(h, LBM_EINVAL, "raw_mean is NULL");
+    if ((rc = flush_sample(h, as_stream(stream))) != LBM_OK) return rc;
     double acc[LBM_NRAW + 1];
     if ((rc = read_res(h, as_stream(stream), lbmk::kResAcc, LBM_NRAW + 1, acc)) != LBM_OK) return rc;
     const double n = acc[LBM_NRAW];
@@ -337,6 +356,7 @@ int lbm_reset_averages(lbm_t *h, void *stream) {
     hipError_t e = lbmk::launch_reset_acc(h, as_stream(stream));
     if (e != hipSuccess) return hip_fail(h, e, "reset averages");
     h->samples = 0;
+    h->pending_sample = false;
     return LBM_OK;
 }
 
@@ -424,6 +444,7 @@ int lbm_save(lbm_t *h, const char *path, void *stream) {
     if (rc) return rc;
     if (!path) return fail(h, LBM_EINVAL, "path is NULL");
     hipStream_t s = as_stream(stream);
+    if ((rc = flush_sample(h, s)) != LBM_OK) return rc;
     CkptHeader c{};
     std::memcpy(c.magic, kCkptMagic, 8);
     c.version = 1;
@@ -516,6 +537,7 @@ int lbm_load(lbm_t *h, const char *path, void *stream) {
     h->t = c.t;
     h->samples = c.samples;
     h->has_flux = false;
+    h->pending_sample = false;
     h->initialised = true;
     if ((e = lbmk::launch_snapshot(h, s)) != hipSuccess) return hip_fail(h, e, "snapshot");
     return LBM_OK;
@@ -563,6 +585,33 @@ int lbm_profile_read(lbm_t *h, double *kernel_ms, int64_t *kernels) {
     *kernel_ms = total;
     *kernels = static_cast<int64_t>(h->events_used / 2);
     h->events_used = 0;
+    return LBM_OK;
+}
+
+int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src || bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 ||
+        reinterpret_cast<uintptr_t>(src) % 16)
+        return LBM_EINVAL;
+    if (bytes == 0) return LBM_OK;
+    const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
+    if (a < b + bytes && b < a + bytes) return LBM_EINVAL;
+    return lbmk::launch_copy(src, dst, bytes, as_stream(stream)) == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+int lbm_nusselt_profile(lbm_t *h, void *stream, double *out) {
+    int rc = require_init(h);
+    if (rc) return rc;
+    if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = lbmk::launch_profile(h, s);
+    if (e != hipSuccess) return hip_fail(h, e, "Nusselt profile");
+    const double *src = reinterpret_cast<const double *>(static_cast<char *>(h->buf) + h->L.off_prof) +
+                        static_cast<size_t>(lbmk::kProfGroups) * 2 * h->p.N;
+    e = hipMemcpyAsync(out, src, h->p.N * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "reading the Nusselt profile");
+    for (int k = 0; k < h->p.N; ++k)
+        if (!std::isfinite(out[k])) return fail(h, LBM_EDIVERGED, "non-finite Nusselt profile");
     return LBM_OK;
 }
 

@@ -356,6 +356,9 @@ __device__ __forceinline__ Macro<R> macros(const R f[kQF], const R h[kQG], const
     m.jy = (f[3] - f[4]) + (f[7] - f[10]) + (f[8] - f[9]) + (f[15] - f[18]) - (f[16] - f[17]);
     m.jz = (f[5] - f[6]) + (f[11] - f[14]) + (f[12] - f[13]) + (f[15] - f[18]) + (f[16] - f[17]);
     m.T = h[0] + (h[1] + h[2]) + (h[3] + h[4]) + (h[5] + h[6]);
+    // a density deviation beyond what the storage represents marks the node
+    // as diverged (NaN), which the FP32 thermal populations then carry
+    if (!(fabs(m.drho) <= c.drho_max)) m.drho = static_cast<R>(NAN);
     m.rho = R(1) + m.drho;
     m.Fz = m.rho * c.gbeta * (m.T - c.T0);
     m.jz += R(0.5) * m.Fz;
@@ -504,15 +507,59 @@ __device__ __forceinline__ Macro<R> collide(R f[kQF], R h[kQG], const Coef<R> &c
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <class C, int CELL, bool SW>
+// Observation outputs of a sample step: the planes [rho - 1, u, v, w, T] of
+// the pre-collision state in the arithmetic type (N^3 values each, x
+// fastest) and the heat that entered through each isothermal wall link during
+// the step that produced the state (2 N^2 FP64 values: hot wall, cold wall).
+template <class R>
+struct ObsOut {
+    R *planes;
+    double *wall;
+    double abb_hot, abb_cold;
+};
+
+// Wall heat flux of the last step at an isothermal wall node: the population
+// that came back from the wall is g_in = -g_out+ + abb, so abb - 2 g_out+
+// equals 2 g_in - abb (Sec. 2.3 anti-bounce-back).  h: pre-collision g.
+template <int CELL, class R>
+__device__ __forceinline__ void write_wall_flux(const ObsOut<R> &o, const Geo &g, const Node &d,
+                                                const R h[kQG]) {
+    if constexpr (CELL == LBM_SIDE_HEATED) {
+        const uint64_t w2 = d.y + static_cast<uint64_t>(g.N) * d.z;
+        if (d.x == 0) o.wall[w2] = 2.0 * static_cast<double>(h[1]) - o.abb_hot;
+        if (d.x == g.N - 1) o.wall[g.N2 + w2] = 2.0 * static_cast<double>(h[2]) - o.abb_cold;
+    } else {
+        const uint64_t w2 = d.x + static_cast<uint64_t>(g.N) * d.y;
+        if (d.z == 0) o.wall[w2] = 2.0 * static_cast<double>(h[5]) - o.abb_hot;
+        if (d.z == g.N - 1) o.wall[g.N2 + w2] = 2.0 * static_cast<double>(h[6]) - o.abb_cold;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void write_planes(const ObsOut<R> &o, const Geo &g, const Node &d,
+                                             const Macro<R> &m) {
+    const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+    o.planes[d.n] = m.drho;
+    o.planes[V + d.n] = m.ux;
+    o.planes[2 * V + d.n] = m.uy;
+    o.planes[3 * V + d.n] = m.uz;
+    o.planes[4 * V + d.n] = m.T;
+}
+
+// One coupled time step of every node.  OBS (sample steps only): also write
+// the observation planes of the pre-collision state from the registers, so
+// that the observables need no second pass over the populations.
+template <class C, int CELL, bool SW, bool OBS>
 __global__ __launch_bounds__(256) void k_step(typename C::S *__restrict__ pop, Geo g,
-                                              Coef<typename C::R> c) {
+                                              Coef<typename C::R> c, ObsOut<typename C::R> o) {
     using R = typename C::R;
     Node d;
     if (!node_of(g, d)) return;
     R f[kQF], h[kQG];
     gather<C, CELL, SW>(pop, g, d, c, f, h);
-    collide(f, h, c);
+    if constexpr (OBS) write_wall_flux<CELL>(o, g, d, h);
+    const Macro<R> m = collide(f, h, c);
+    if constexpr (OBS) write_planes(o, g, d, m);
     scatter<C, CELL, SW>(pop, g, d, c, f, h);
 }
 
@@ -671,15 +718,11 @@ __global__ __launch_bounds__(256) void k_get_pop(const typename C::S *__restrict
     for (int j = 0; j < kQG; ++j) out[(kQF + j) * V + d.n] = static_cast<double>(h[j]);
 }
 
-// Macro planes [rho, u, v, w, T] and, at the isothermal walls, the heat that
-// entered through each wall link during the last step: the population that
-// came back from the wall is g_in = -g_out+ + abb, so abb - 2 g_out+ equals
-// 2 g_in - abb (Sec. 2.3 anti-bounce-back).
+// FP64 macro planes [rho, u, v, w, T] of the current state (field output,
+// residual, diagnostics).
 template <class C, int CELL, bool SW>
 __global__ __launch_bounds__(256) void k_macro(const typename C::S *__restrict__ pop, Geo g,
-                                               Coef<typename C::R> c, double *__restrict__ macro,
-                                               double *__restrict__ wall, double abb_hot,
-                                               double abb_cold) {
+                                               Coef<typename C::R> c, double *__restrict__ macro) {
     using R = typename C::R;
     Node d;
     if (!node_of(g, d)) return;
@@ -692,16 +735,20 @@ __global__ __launch_bounds__(256) void k_macro(const typename C::S *__restrict__
     macro[2 * V + d.n] = m.uy;
     macro[3 * V + d.n] = m.uz;
     macro[4 * V + d.n] = m.T;
-    if (wall == nullptr) return;
-    if constexpr (CELL == LBM_SIDE_HEATED) {
-        const uint64_t w2 = d.y + static_cast<uint64_t>(g.N) * d.z;
-        if (d.x == 0) wall[w2] = 2.0 * static_cast<double>(h[1]) - abb_hot;
-        if (d.x == g.N - 1) wall[g.N2 + w2] = 2.0 * static_cast<double>(h[2]) - abb_cold;
-    } else {
-        const uint64_t w2 = d.x + static_cast<uint64_t>(g.N) * d.y;
-        if (d.z == 0) wall[w2] = 2.0 * static_cast<double>(h[5]) - abb_hot;
-        if (d.z == g.N - 1) wall[g.N2 + w2] = 2.0 * static_cast<double>(h[6]) - abb_cold;
-    }
+}
+
+// Observation planes and wall flux of the current state outside a step (the
+// same values the OBS step kernel writes for the state it starts from).
+template <class C, int CELL, bool SW>
+__global__ __launch_bounds__(256) void k_obs_planes(const typename C::S *__restrict__ pop, Geo g,
+                                                    Coef<typename C::R> c, ObsOut<typename C::R> o) {
+    using R = typename C::R;
+    Node d;
+    if (!node_of(g, d)) return;
+    R f[kQF], h[kQG];
+    gather<C, CELL, SW>(pop, g, d, c, f, h);
+    if (o.wall) write_wall_flux<CELL>(o, g, d, h);
+    write_planes(o, g, d, macros(f, h, c));
 }
 
 // ---------------------------------------------------------------------------
@@ -730,94 +777,133 @@ __device__ __forceinline__ void block_reduce_to(double (&v)[K], double *__restri
     }
 }
 
-// One-sided / central derivative of a plane along one axis (stride s between
-// neighbours, k the node's index on that axis).  See the header of lbm.h.
-__device__ __forceinline__ double dfd(const double *__restrict__ phi, uint64_t n, int64_t s, int k,
-                                      int N, double w_lo, double w_hi, bool mirror) {
-    if (k > 0 && k < N - 1) return 0.5 * (phi[n + s] - phi[n - s]);
-    if (k == 0) {
-        const double a = phi[n], b = phi[n + s];
-        return mirror ? 0.5 * (b - a) : (-4.0 / 3.0) * w_lo + a + b * (1.0 / 3.0);
-    }
-    const double a = phi[n], b = phi[n - s];
-    return mirror ? 0.5 * (a - b) : (4.0 / 3.0) * w_hi - a - b * (1.0 / 3.0);
+// Derivative along one axis at a node with index k on that axis from the
+// values at k-1, k and k+1 (lo and hi unused where they would lie outside):
+// central inside; at the first node next to a wall the quadratic through the
+// wall value (w_lo or w_hi) half a cell away and the two nearest nodes, or
+// with a mirror node (dphi/dn = 0) at an adiabatic wall.
+__device__ __forceinline__ double dfd(double lo, double c, double hi, int k, int N, double w_lo,
+                                      double w_hi, bool mirror) {
+    if (k > 0 && k < N - 1) return 0.5 * (hi - lo);
+    if (k == 0) return mirror ? 0.5 * (hi - c) : (-4.0 / 3.0) * w_lo + c + hi * (1.0 / 3.0);
+    return mirror ? 0.5 * (c - lo) : (4.0 / 3.0) * w_hi - c - lo * (1.0 / 3.0);
 }
 
 struct ObsArgs {
     double nu, kappa, T_hot, T_cold;
 };
 
-template <int CELL>
-__global__ __launch_bounds__(kRedBlock) void k_observe(Geo g, ObsArgs a,
-                                                       const double *__restrict__ macro,
+// z-planes per block of the observable reduction.
+constexpr int kObsZ = 16;
+
+// Observable partial sums from the observation planes [rho - 1, u, v, w, T]
+// (type P) and the wall flux (NULL before the first step).  A block takes 256
+// consecutive in-plane nodes r and marches them through kObsZ planes: the
+// values at z - 1, z and z + 1 stay in registers, the in-plane neighbours
+// r +- 1 and r +- N are read from the lines the block and its neighbours load
+// at the same time, so each plane value comes from HBM once.  Logical block
+// lb = chunk * ntile + tile; every block writes one row of partials.
+template <int CELL, class P>
+__global__ __launch_bounds__(kRedBlock) void k_observe(int N, uint32_t ntile, ObsArgs a,
+                                                       const P *__restrict__ pl,
                                                        const double *__restrict__ wall,
                                                        double *__restrict__ part) {
-    Node d;
-    const bool live = node_of(g, d);
+    const uint32_t lb = xcd_order();
+    const uint32_t tile = lb % ntile, chunk = lb / ntile;
+    const uint32_t N2 = static_cast<uint32_t>(N) * N;
+    const uint32_t r = tile * kRedBlock + threadIdx.x;
     double v[LBM_NRAW];
 #pragma unroll
     for (int k = 0; k < LBM_NRAW; ++k) v[k] = 0.0;
-    if (live) {
-        const int N = g.N;
-        const uint64_t V = static_cast<uint64_t>(g.N2) * N;
-        const double *rho = macro, *T = macro + 4 * V;
-        const double *U[3] = {macro + V, macro + 2 * V, macro + 3 * V};
-        const uint64_t n = d.n;
-        const int c3[3] = {d.x, d.y, d.z};
-        const int64_t st[3] = {1, N, static_cast<int64_t>(g.N2)};
+    if (r < N2) {
+        const uint64_t V = static_cast<uint64_t>(N2) * N;
+        const P *D = pl, *F[4] = {pl + V, pl + 2 * V, pl + 3 * V, pl + 4 * V};   // u, v, w, T
+        const int y = static_cast<int>(r / N), x = static_cast<int>(r) - y * N;
+        const int z0 = static_cast<int>(chunk) * kObsZ, z1 = min(N, z0 + kObsZ);
         constexpr int iso = CELL == LBM_SIDE_HEATED ? 0 : 2;
-        double du[3][3];
+        const int mid_lo = (N - 1) / 2, mid_hi = N / 2;
+        const double wm = (y == mid_lo || y == mid_hi) ? (mid_lo == mid_hi ? 1.0 : 0.5) : 0.0;
+        double lo[4], c[4], hi[4];   // (u, v, w, T) at z - 1, z, z + 1
+        {
+            const uint64_t n = r + static_cast<uint64_t>(z0) * N2;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int q = 0; q < 4; ++q) {
+                c[q] = static_cast<double>(F[q][n]);
+                lo[q] = z0 > 0 ? static_cast<double>(F[q][n - N2]) : 0.0;
+            }
+        }
+        for (int z = z0; z < z1; ++z) {
+            const uint64_t n = r + static_cast<uint64_t>(z) * N2;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) du[i][j] = dfd(U[j], n, st[i], c3[i], N, 0.0, 0.0, false);
-        double dT[3];
+            for (int q = 0; q < 4; ++q) hi[q] = z + 1 < N ? static_cast<double>(F[q][n + N2]) : 0.0;
+            double xl[4], xh[4], yl[4], yh[4];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) dT[i] = dfd(T, n, st[i], c3[i], N, a.T_hot, a.T_cold, i != iso);
-        double eu = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int q = 0; q < 4; ++q) {
+                xl[q] = x > 0 ? static_cast<double>(F[q][n - 1]) : 0.0;
+                xh[q] = x < N - 1 ? static_cast<double>(F[q][n + 1]) : 0.0;
+                yl[q] = y > 0 ? static_cast<double>(F[q][n - N]) : 0.0;
+                yh[q] = y < N - 1 ? static_cast<double>(F[q][n + N]) : 0.0;
+            }
+            const int c3[3] = {x, y, z};
+            double du[3][3];   // du[i][j] = d_i u_j
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const double sij = du[i][j] + du[j][i];
-                eu += sij * sij;
+                du[0][j] = dfd(xl[j], c[j], xh[j], x, N, 0.0, 0.0, false);
+                du[1][j] = dfd(yl[j], c[j], yh[j], y, N, 0.0, 0.0, false);
+                du[2][j] = dfd(lo[j], c[j], hi[j], z, N, 0.0, 0.0, false);
             }
-        const double u = U[0][n], vv = U[1][n], w = U[2][n], Tn = T[n], dr = rho[n] - 1.0;
-        const double div = du[0][0] + du[1][1] + du[2][2];
-        v[LBM_RAW_U2] = u * u + vv * vv + w * w;
-        v[LBM_RAW_W2] = w * w;
-        v[LBM_RAW_WT] = w * Tn;
-        v[LBM_RAW_UT] = u * Tn;
-        v[LBM_RAW_EPS_U] = 0.5 * a.nu * eu;
-        v[LBM_RAW_EPS_T] = a.kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
-        v[LBM_RAW_DRHO2] = dr * dr;
-        v[LBM_RAW_T] = Tn;
-        v[LBM_RAW_DRHO] = dr;
-        v[LBM_RAW_DIV2] = div * div;
-        const int k = c3[iso];
-        const int mid_lo = (N - 1) / 2, mid_hi = N / 2;
-        const double wm = (d.y == mid_lo || d.y == mid_hi) ? (mid_lo == mid_hi ? 1.0 : 0.5) : 0.0;
-        const uint64_t w2 = CELL == LBM_SIDE_HEATED ? d.y + static_cast<uint64_t>(N) * d.z
-                                                    : d.x + static_cast<uint64_t>(N) * d.y;
-        if (k == 0) {
-            const double q = wall ? wall[w2] : 0.0;
-            const double gr = -(-8.0 * a.T_hot + 9.0 * Tn - T[n + st[iso]]) * (1.0 / 3.0);
-            v[LBM_RAW_FLUX_HOT] = q;
-            v[LBM_RAW_FLUX_HOT_MID] = wm * q;
-            v[LBM_RAW_GRAD_HOT] = gr;
-            v[LBM_RAW_GRAD_HOT_MID] = wm * gr;
-        }
-        if (k == N - 1) {
-            const double q = wall ? wall[g.N2 + w2] : 0.0;
-            const double gr = (8.0 * a.T_cold - 9.0 * Tn + T[n - st[iso]]) * (1.0 / 3.0);
-            v[LBM_RAW_FLUX_COLD] = q;
-            v[LBM_RAW_FLUX_COLD_MID] = wm * q;
-            v[LBM_RAW_GRAD_COLD] = gr;
-            v[LBM_RAW_GRAD_COLD_MID] = wm * gr;
+            const double dT[3] = {dfd(xl[3], c[3], xh[3], x, N, a.T_hot, a.T_cold, iso != 0),
+                                  dfd(yl[3], c[3], yh[3], y, N, a.T_hot, a.T_cold, true),
+                                  dfd(lo[3], c[3], hi[3], z, N, a.T_hot, a.T_cold, iso != 2)};
+            double eu = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double sij = du[i][j] + du[j][i];
+                    eu += sij * sij;
+                }
+            const double u = c[0], vv = c[1], w = c[2], Tn = c[3];
+            const double dr = static_cast<double>(D[n]);
+            const double div = du[0][0] + du[1][1] + du[2][2];
+            v[LBM_RAW_U2] += u * u + vv * vv + w * w;
+            v[LBM_RAW_W2] += w * w;
+            v[LBM_RAW_WT] += w * Tn;
+            v[LBM_RAW_UT] += u * Tn;
+            v[LBM_RAW_EPS_U] += 0.5 * a.nu * eu;
+            v[LBM_RAW_EPS_T] += a.kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
+            v[LBM_RAW_DRHO2] += dr * dr;
+            v[LBM_RAW_T] += Tn;
+            v[LBM_RAW_DRHO] += dr;
+            v[LBM_RAW_DIV2] += div * div;
+            const int k = c3[iso];
+            const double T_in = iso == 0 ? (k == 0 ? xh[3] : xl[3]) : (k == 0 ? hi[3] : lo[3]);
+            const uint64_t w2 = CELL == LBM_SIDE_HEATED ? y + static_cast<uint64_t>(N) * z
+                                                        : x + static_cast<uint64_t>(N) * y;
+            if (k == 0) {
+                const double q = wall ? wall[w2] : 0.0;
+                const double gr = -(-8.0 * a.T_hot + 9.0 * Tn - T_in) * (1.0 / 3.0);
+                v[LBM_RAW_FLUX_HOT] += q;
+                v[LBM_RAW_FLUX_HOT_MID] += wm * q;
+                v[LBM_RAW_GRAD_HOT] += gr;
+                v[LBM_RAW_GRAD_HOT_MID] += wm * gr;
+            }
+            if (k == N - 1) {
+                const double q = wall ? wall[N2 + w2] : 0.0;
+                const double gr = (8.0 * a.T_cold - 9.0 * Tn + T_in) * (1.0 / 3.0);
+                v[LBM_RAW_FLUX_COLD] += q;
+                v[LBM_RAW_FLUX_COLD_MID] += wm * q;
+                v[LBM_RAW_GRAD_COLD] += gr;
+                v[LBM_RAW_GRAD_COLD_MID] += wm * gr;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lo[q] = c[q];
+                c[q] = hi[q];
+            }
         }
     }
-    const uint32_t b = blockIdx.x;
-    block_reduce_to<LBM_NRAW, false>(v, part + static_cast<uint64_t>(b) * kNPart);
+    block_reduce_to<LBM_NRAW, false>(v, part + static_cast<uint64_t>(lb) * kNPart);
 }
 
 // First level of the partial reduction: block b folds rows [b*per, (b+1)*per)
@@ -913,6 +999,86 @@ __global__ __launch_bounds__(kRedBlock) void k_centerline(int N, const double *_
     }
 }
 
+// Plane sums for the Nusselt profile across the cell: for node plane k of
+// the isothermal axis a (x side-heated, z Rayleigh-Benard), row group g adds
+// u_a T and d_a T (the differences of the observables) over its share of the
+// plane into part[g][2k] and part[g][2k + 1].  Side-heated: a thread owns one
+// x and walks the rows (y, z) = g, g + kProfG, ...; Rayleigh-Benard: block
+// (z, g) walks r = g 256 + t, stepping kProfG 256, and reduces.
+constexpr int kProfG = kProfGroups;
+
+template <int CELL>
+__global__ __launch_bounds__(kRedBlock) void k_profile(int N, const double *__restrict__ macro,
+                                                       double T_hot, double T_cold,
+                                                       double *__restrict__ part) {
+    const uint32_t N2 = static_cast<uint32_t>(N) * N;
+    const uint64_t V = static_cast<uint64_t>(N2) * N;
+    const double *T = macro + 4 * V;
+    const uint32_t grp = blockIdx.y;
+    double *out = part + static_cast<uint64_t>(grp) * 2 * N;
+    if constexpr (CELL == LBM_SIDE_HEATED) {
+        const int x = blockIdx.x * kRedBlock + threadIdx.x;
+        if (x >= N) return;
+        const double *ua = macro + V;
+        double conv = 0.0, cond = 0.0;
+        for (uint32_t row = grp; row < N2; row += kProfG) {
+            const uint64_t n = x + static_cast<uint64_t>(N) * row;
+            const double t = T[n];
+            conv += ua[n] * t;
+            cond += dfd(x > 0 ? T[n - 1] : 0.0, t, x < N - 1 ? T[n + 1] : 0.0, x, N, T_hot, T_cold, false);
+        }
+        out[2 * x] = conv;
+        out[2 * x + 1] = cond;
+    } else {
+        const int z = blockIdx.x;
+        const double *ua = macro + 3 * V;
+        double v[2] = {0.0, 0.0};
+        for (uint32_t r = grp * kRedBlock + threadIdx.x; r < N2; r += kProfG * kRedBlock) {
+            const uint64_t n = r + static_cast<uint64_t>(N2) * z;
+            const double t = T[n];
+            v[0] += ua[n] * t;
+            v[1] += dfd(z > 0 ? T[n - N2] : 0.0, t, z < N - 1 ? T[n + N2] : 0.0, z, N, T_hot, T_cold, false);
+        }
+        block_reduce_to<2, false>(v, out + 2 * z);
+    }
+}
+
+// Nu(k) = H/(kappa dT) (<u_a T>_k - kappa <d_a T>_k) from the group sums,
+// added in a fixed order.
+__global__ __launch_bounds__(kRedBlock) void k_profile_final(int N, const double *__restrict__ part,
+                                                             double scale, double kappa,
+                                                             double *__restrict__ nu) {
+    const double inv_A = 1.0 / (static_cast<double>(N) * N);
+    for (int k = threadIdx.x; k < N; k += kRedBlock) {
+        double conv = 0.0, cond = 0.0;
+        for (int g = 0; g < kProfG; ++g) {
+            conv += part[static_cast<uint64_t>(g) * 2 * N + 2 * k];
+            cond += part[static_cast<uint64_t>(g) * 2 * N + 2 * k + 1];
+        }
+        nu[k] = scale * (conv * inv_A - kappa * cond * inv_A);
+    }
+}
+
+// Reference copy: 16-byte streaming loads and stores, four in flight per
+// thread, a grid-stride loop over n16 16-byte words.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                              uint64_t n16) {
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(src + i);
+        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 __global__ void k_reset_acc(double *__restrict__ res) {
     if (threadIdx.x <= LBM_NRAW) res[kResAcc + threadIdx.x] = 0.0;
 }
@@ -985,6 +1151,10 @@ Coef<R> make_coef(const lbm_t *h) {
     c.isf = static_cast<R>(half ? 1.0 / 1024.0 : 1.0);
     c.sg = static_cast<R>(1.0);
     c.isg = static_cast<R>(1.0);
+    // FP16C cannot hold inf or NaN (it clamps at |f_i - w_i| = 1/4), so a
+    // blow-up would go on with clamped values; a density deviation of 0.1,
+    // several times what any flow at Mach <= 0.1 reaches, marks it instead
+    c.drho_max = static_cast<R>(h->storage == LBM_FP16C ? 0.1 : INFINITY);
     return c;
 }
 
@@ -1017,10 +1187,26 @@ hipError_t with_codec(const lbm_t *h, F &&fn) {
     }
 }
 
-template <class C, int CELL, bool SW>
+template <class R>
+ObsOut<R> obs_out(const lbm_t *h) {
+    ObsOut<R> o;
+    o.planes = reinterpret_cast<R *>(static_cast<char *>(h->buf) + h->L.off_macro);
+    o.wall = dptr(h, h->L.off_wall);
+    o.abb_hot = (6.0 + h->p.a_T) / 21.0 * h->p.T_hot;
+    o.abb_cold = (6.0 + h->p.a_T) / 21.0 * h->p.T_cold;
+    return o;
+}
+
+template <class C, int CELL, bool SW, bool OBS>
 void step_one(const lbm_t *h, hipStream_t s) {
-    k_step<C, CELL, SW><<<grid_of(h, h->block), h->block, lds_cap_bytes(h->waves[SW], h->block), s>>>(
-        pop_ptr<C>(h), geo_for(h, h->block), make_coef<typename C::R>(h));
+    k_step<C, CELL, SW, OBS><<<grid_of(h, h->block), h->block, lds_cap_bytes(h->waves[SW], h->block), s>>>(
+        pop_ptr<C>(h), geo_for(h, h->block), make_coef<typename C::R>(h), obs_out<typename C::R>(h));
+}
+
+template <class C, int CELL, bool OBS>
+void step_parity(const lbm_t *h, int parity, hipStream_t s) {
+    if (parity) step_one<C, CELL, true, OBS>(h, s);
+    else step_one<C, CELL, false, OBS>(h, s);
 }
 
 }  // namespace
@@ -1028,15 +1214,15 @@ void step_one(const lbm_t *h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_step(const lbm_t *h, int parity, hipStream_t s) {
+hipError_t launch_step(const lbm_t *h, int parity, bool obs, hipStream_t s) {
     return with_codec(h, [&](auto cd) {
         using C = decltype(cd);
         if (h->p.cell == LBM_SIDE_HEATED) {
-            if (parity) step_one<C, LBM_SIDE_HEATED, true>(h, s);
-            else step_one<C, LBM_SIDE_HEATED, false>(h, s);
+            if (obs) step_parity<C, LBM_SIDE_HEATED, true>(h, parity, s);
+            else step_parity<C, LBM_SIDE_HEATED, false>(h, parity, s);
         } else {
-            if (parity) step_one<C, LBM_RAYLEIGH_BENARD, true>(h, s);
-            else step_one<C, LBM_RAYLEIGH_BENARD, false>(h, s);
+            if (obs) step_parity<C, LBM_RAYLEIGH_BENARD, true>(h, parity, s);
+            else step_parity<C, LBM_RAYLEIGH_BENARD, false>(h, parity, s);
         }
         return hipGetLastError();
     });
@@ -1128,7 +1314,7 @@ void default_waves(int storage, int out[2]) {
 
 hipError_t launch_resample(const lbm_t *h, int M, float *out, hipStream_t s) {
     double *macro = dptr(h, h->L.off_macro);
-    hipError_t e = launch_macro(h, macro, nullptr, s);
+    hipError_t e = launch_macro(h, macro, s);
     if (e != hipSuccess) return e;
     const uint64_t M3 = static_cast<uint64_t>(M) * M * M;
     k_resample<<<static_cast<uint32_t>((M3 + 255) / 256), 256, 0, s>>>(
@@ -1172,49 +1358,86 @@ hipError_t launch_get_pop(const lbm_t *h, double *out, hipStream_t s) {
     });
 }
 
-hipError_t launch_macro(const lbm_t *h, double *macro_out, double *wall_out, hipStream_t s) {
-    const double abb_hot = (6.0 + h->p.a_T) / 21.0 * h->p.T_hot;
-    const double abb_cold = (6.0 + h->p.a_T) / 21.0 * h->p.T_cold;
+hipError_t launch_macro(const lbm_t *h, double *macro_out, hipStream_t s) {
     return with_codec(h, [&](auto cd) {
         using C = decltype(cd);
         auto c = make_coef<typename C::R>(h);
         const dim3 gr = grid_of(h, 256);
+        const Geo g = geo_for(h, 256);
         const typename C::S *p = pop_ptr<C>(h);
         if (h->p.cell == LBM_SIDE_HEATED) {
-            if (h->parity)
-                k_macro<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
-            else
-                k_macro<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
+            if (h->parity) k_macro<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, g, c, macro_out);
+            else k_macro<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, g, c, macro_out);
         } else {
-            if (h->parity)
-                k_macro<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
-            else
-                k_macro<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, geo_for(h, 256), c, macro_out, wall_out, abb_hot, abb_cold);
+            if (h->parity) k_macro<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, g, c, macro_out);
+            else k_macro<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, g, c, macro_out);
         }
         return hipGetLastError();
     });
 }
 
-hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s) {
-    double *macro = dptr(h, h->L.off_macro);
-    double *wall = h->has_flux ? dptr(h, h->L.off_wall) : nullptr;
-    hipError_t e = launch_macro(h, macro, dptr(h, h->L.off_wall), s);
-    if (e != hipSuccess) return e;
-    ObsArgs a{h->p.nu, h->p.kappa, h->p.T_hot, h->p.T_cold};
+hipError_t launch_obs_planes(const lbm_t *h, hipStream_t s) {
+    return with_codec(h, [&](auto cd) {
+        using C = decltype(cd);
+        auto c = make_coef<typename C::R>(h);
+        auto o = obs_out<typename C::R>(h);
+        const dim3 gr = grid_of(h, 256);
+        const Geo g = geo_for(h, 256);
+        const typename C::S *p = pop_ptr<C>(h);
+        if (h->p.cell == LBM_SIDE_HEATED) {
+            if (h->parity) k_obs_planes<C, LBM_SIDE_HEATED, true><<<gr, 256, 0, s>>>(p, g, c, o);
+            else k_obs_planes<C, LBM_SIDE_HEATED, false><<<gr, 256, 0, s>>>(p, g, c, o);
+        } else {
+            if (h->parity) k_obs_planes<C, LBM_RAYLEIGH_BENARD, true><<<gr, 256, 0, s>>>(p, g, c, o);
+            else k_obs_planes<C, LBM_RAYLEIGH_BENARD, false><<<gr, 256, 0, s>>>(p, g, c, o);
+        }
+        return hipGetLastError();
+    });
+}
+
+uint32_t observe_tiles(int N) { return (static_cast<uint32_t>(N) * N + kRedBlock - 1) / kRedBlock; }
+uint32_t observe_blocks(int N) { return observe_tiles(N) * ((N + kObsZ - 1) / kObsZ); }
+
+hipError_t launch_observe_reduce(const lbm_t *h, bool accumulate, hipStream_t s) {
+    const int N = h->geo.N;
+    const double *wall = h->has_flux ? dptr(h, h->L.off_wall) : nullptr;
+    const ObsArgs a{h->p.nu, h->p.kappa, h->p.T_hot, h->p.T_cold};
     double *part = dptr(h, h->L.off_part);
-    const dim3 gr = grid_of(h, kRedBlock);
-    if (h->p.cell == LBM_SIDE_HEATED)
-        k_observe<LBM_SIDE_HEATED><<<gr, kRedBlock, 0, s>>>(geo_for(h, kRedBlock), a, macro, wall, part);
-    else
-        k_observe<LBM_RAYLEIGH_BENARD><<<gr, kRedBlock, 0, s>>>(geo_for(h, kRedBlock), a, macro, wall, part);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const double N = h->geo.N;
+    const uint32_t ntile = observe_tiles(N), nblk = observe_blocks(N);
+    hipError_t e = with_codec(h, [&](auto cd) {
+        using R = typename decltype(cd)::R;
+        const R *pl = reinterpret_cast<const R *>(static_cast<char *>(h->buf) + h->L.off_macro);
+        if (h->p.cell == LBM_SIDE_HEATED)
+            k_observe<LBM_SIDE_HEATED, R><<<nblk, kRedBlock, 0, s>>>(N, ntile, a, pl, wall, part);
+        else
+            k_observe<LBM_RAYLEIGH_BENARD, R><<<nblk, kRedBlock, 0, s>>>(N, ntile, a, pl, wall, part);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    const double Nd = N;
     double *fold = dptr(h, h->L.off_fold);
-    const uint32_t per = (h->L.nblk_red + kFold - 1) / kFold;
-    k_fold_rows<LBM_NRAW, false><<<kFold, kRedBlock, 0, s>>>(part, h->L.nblk_red, per, fold);
+    const uint32_t per = (nblk + kFold - 1) / kFold;
+    k_fold_rows<LBM_NRAW, false><<<kFold, kRedBlock, 0, s>>>(part, nblk, per, fold);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_finalize_obs<<<1, kRedBlock, 0, s>>>(fold, kFold, 1.0 / (N * N * N), 1.0 / (N * N), 1.0 / N,
+    k_finalize_obs<<<1, kRedBlock, 0, s>>>(fold, kFold, 1.0 / (Nd * Nd * Nd), 1.0 / (Nd * Nd), 1.0 / Nd,
                                            dptr(h, h->L.off_res), accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s) {
+    hipError_t e = launch_obs_planes(h, s);
+    if (e != hipSuccess) return e;
+    return launch_observe_reduce(h, accumulate, s);
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const uint64_t n16 = bytes / 16;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t want = (n16 + 255) / 256;
+    const uint32_t blocks = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(want, 16ull * cus)));
+    k_copy<<<blocks, 256, 0, s>>>(static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n16);
     return hipGetLastError();
 }
 
@@ -1225,7 +1448,7 @@ hipError_t launch_reset_acc(const lbm_t *h, hipStream_t s) {
 
 hipError_t launch_residual(const lbm_t *h, hipStream_t s) {
     double *macro = dptr(h, h->L.off_macro);
-    hipError_t e = launch_macro(h, macro, nullptr, s);
+    hipError_t e = launch_macro(h, macro, s);
     if (e != hipSuccess) return e;
     double *part = dptr(h, h->L.off_part);
     k_residual<<<grid_of(h, kRedBlock), kRedBlock, 0, s>>>(geo_for(h, kRedBlock), macro, dptr(h, h->L.off_snap), part);
@@ -1240,15 +1463,33 @@ hipError_t launch_residual(const lbm_t *h, hipStream_t s) {
 
 hipError_t launch_centerline(const lbm_t *h, hipStream_t s) {
     double *macro = dptr(h, h->L.off_macro);
-    hipError_t e = launch_macro(h, macro, nullptr, s);
+    hipError_t e = launch_macro(h, macro, s);
     if (e != hipSuccess) return e;
     k_centerline<<<2, kRedBlock, 0, s>>>(h->geo.N, macro, dptr(h, h->L.off_res));
     return hipGetLastError();
 }
 
+hipError_t launch_profile(const lbm_t *h, hipStream_t s) {
+    double *macro = dptr(h, h->L.off_macro);
+    hipError_t e = launch_macro(h, macro, s);
+    if (e != hipSuccess) return e;
+    const int N = h->geo.N;
+    double *part = dptr(h, h->L.off_prof);
+    if (h->p.cell == LBM_SIDE_HEATED)
+        k_profile<LBM_SIDE_HEATED><<<dim3((N + kRedBlock - 1) / kRedBlock, kProfG), kRedBlock, 0, s>>>(
+            N, macro, h->p.T_hot, h->p.T_cold, part);
+    else
+        k_profile<LBM_RAYLEIGH_BENARD><<<dim3(N, kProfG), kRedBlock, 0, s>>>(N, macro, h->p.T_hot,
+                                                                           h->p.T_cold, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_profile_final<<<1, kRedBlock, 0, s>>>(N, part, h->p.H / (h->p.kappa * h->p.dT), h->p.kappa,
+                                            part + static_cast<uint64_t>(kProfG) * 2 * N);
+    return hipGetLastError();
+}
+
 hipError_t launch_snapshot(const lbm_t *h, hipStream_t s) {
     double *macro = dptr(h, h->L.off_macro);
-    hipError_t e = launch_macro(h, macro, nullptr, s);
+    hipError_t e = launch_macro(h, macro, s);
     if (e != hipSuccess) return e;
     const uint64_t V = static_cast<uint64_t>(h->geo.N2) * h->geo.N;
     return hipMemcpyAsync(dptr(h, h->L.off_snap), macro + V, 4 * V * sizeof(double),
@@ -1289,6 +1530,8 @@ Layout make_layout(int N, int storage) {
     o = up(o + static_cast<size_t>(kFold) * kNPart * sizeof(double));
     L.off_res = o;
     o = up(o + kResDoubles * sizeof(double));
+    L.off_prof = o;   // Nusselt profile: kProfG row-group sums of 2 N, then N values
+    o = up(o + (static_cast<size_t>(kProfG) * 2 + 1) * N * sizeof(double));
     L.total = o;
     return L;
 }

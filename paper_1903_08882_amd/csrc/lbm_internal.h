@@ -31,6 +31,7 @@ struct Coef {
     R abb_hot, abb_cold;     // (6 + a_T)/21 * T_w of the hot and cold walls
     R sf, isf;               // storage scale of f deviations and its inverse
     R sg, isg;               // storage scale of g and its inverse
+    R drho_max;              // |rho - 1| above this marks a node as diverged
 };
 
 // Geometry of one launch: gx = ceil(N^2 / block) blocks per z-plane, gx * N
@@ -65,7 +66,7 @@ struct Layout {
     uint64_t slab = 0;       // storage bytes per z-plane
     uint64_t pop_bytes = 0;  // storage bytes of all populations
     size_t off_pop = 0, off_macro = 0, off_snap = 0, off_wall = 0;
-    size_t off_part = 0, off_fold = 0, off_res = 0, total = 0;
+    size_t off_part = 0, off_fold = 0, off_res = 0, off_prof = 0, total = 0;
     uint32_t nblk_red = 0;   // blocks of the node-parallel reduction kernels
 };
 
@@ -88,6 +89,8 @@ struct lbm {
     int64_t samples = 0;     // time-average samples taken
     bool initialised = false;
     bool has_flux = false;   // a step was taken since the populations were set
+    bool pending_sample = false;   // the current state is a sample state whose
+                                   // observables are not yet in the averages
     bool profiling = false;
     bool in_batch = false;   // stepped only through its batch
     std::vector<hipEvent_t> events;
@@ -119,10 +122,18 @@ namespace lbmk {
 hipError_t launch_init(const lbm_t *h, const double *uvwT, hipStream_t s);
 hipError_t launch_set_pop(const lbm_t *h, const double *in, hipStream_t s);
 hipError_t launch_get_pop(const lbm_t *h, double *out, hipStream_t s);
-hipError_t launch_step(const lbm_t *h, int parity, hipStream_t s);
-hipError_t launch_macro(const lbm_t *h, double *macro_out, double *wall_out, hipStream_t s);
-// Reduces the macro planes (and wall fluxes) to the raw vector at res[0..];
-// with accumulate, also adds it to res[32..] and counts the sample.
+// One step; with obs, the step kernel also writes the observation planes
+// [rho - 1, u, v, w, T] (arithmetic type) and wall fluxes of the state it
+// starts from into the macro region (then launch_observe_reduce them).
+hipError_t launch_step(const lbm_t *h, int parity, bool obs, hipStream_t s);
+// FP64 planes [rho, u, v, w, T] of the current state.
+hipError_t launch_macro(const lbm_t *h, double *macro_out, hipStream_t s);
+// Observation planes and wall fluxes of the current state (outside a step).
+hipError_t launch_obs_planes(const lbm_t *h, hipStream_t s);
+// Reduces the observation planes (and wall fluxes) to the raw vector at
+// res[0..]; with accumulate, also adds it to res[32..] and counts the sample.
+hipError_t launch_observe_reduce(const lbm_t *h, bool accumulate, hipStream_t s);
+// launch_obs_planes, then launch_observe_reduce.
 hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s);
 hipError_t launch_reset_acc(const lbm_t *h, hipStream_t s);
 // Residual against the snapshot into res[64..66], then snapshot := current.
@@ -143,6 +154,12 @@ uint32_t lds_cap_bytes(int waves, int block);
 void default_waves(int storage, int out[2]);
 // Centreline maxima of u (over z) and w (over x) into res[kResPeak..+3].
 hipError_t launch_centerline(const lbm_t *h, hipStream_t s);
+// Plane-averaged Nusselt profile across the cell: N values at
+// off_prof + 2 N kProfG doubles (see lbm_nusselt_profile).
+hipError_t launch_profile(const lbm_t *h, hipStream_t s);
+// Streaming 16-byte copy of bytes (a multiple of 16) from src to dst.
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+constexpr int kProfGroups = 64;
 
 // Offsets (in doubles) of the result block.
 constexpr int kResCur = 0;

@@ -283,7 +283,8 @@ def _raw_floor(p):
 @pytest.mark.parametrize("N", [19, 18])
 def test_fields_and_observables(cell, storage, N):
     """Odd and even N: the mid-line observables average the two central rows
-    for even N."""
+    for even N.  Fields, raw observables, the Nusselt profile across the cell
+    and the headline numbers against the oracle."""
     pr = Pair(N, 1e5, 0.71, cell, storage, U=0.1)
     pr.init_rich()
     pr.step(37)
@@ -295,6 +296,10 @@ def test_fields_and_observables(cell, storage, N):
     rg = B.lbm_observables_raw(pr.h)
     ro = pr.o.observables_raw()
     _raw_close(rg, ro, tol * (10 if storage == "fp32" else 1), _raw_floor(pr.p))
+    # the plane-averaged Nusselt profile across the cell
+    pg = np.asarray(B.lbm_nusselt_profile(pr.h))
+    po = pr.o.nusselt_profile()
+    assert np.abs(pg - po).max() <= tol * 10 * max(np.abs(po).max(), 1.0), (pg, po)
     Nu, Re, eu, eT = B.lbm_observables(pr.h)
     nd = oracle.nondimensional(pr.p, ro)
     assert abs(Nu - 0.5 * (nd["Nu_hot"] + nd["Nu_cold"])) <= 1e-3 * abs(nd["Nu_hot"]) + 1e-9
@@ -381,8 +386,14 @@ def test_mass_and_energy_balance_at_any_size(N):
 # Error paths
 # --------------------------------------------------------------------------
 
-def test_errors_before_initialisation_and_on_divergence():
-    h = B.lbm_create(8, 1e4, 0.71, 0, "fp32", B.lbm_default_opts(U=0.1))
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16s", "fp16c"])
+def test_errors_before_initialisation_and_on_divergence(storage):
+    """Stepping before the populations are set is refused; a NaN planted in
+    one population is reported as divergence by the observables and the
+    residual after two steps in every storage (FP16C cannot store NaN: the
+    value is clamped, and the density guard turns the node into NaN, which the
+    FP32 thermal populations keep)."""
+    h = B.lbm_create(8, 1e4, 0.71, 0, storage, B.lbm_default_opts(U=0.1))
     with pytest.raises(B.LBMError) as e:
         B.lbm_step(h, 1)
     assert e.value.status == -6
@@ -400,28 +411,140 @@ def test_errors_before_initialisation_and_on_divergence():
     assert e.value.status == -5
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16c"])
+@pytest.mark.parametrize("cell", [0, 1])
+def test_sample_steps_equal_separate_observation_bitwise(cell, storage):
+    """With sample_every = K the step that leaves a sample state observes it
+    from the populations it loads (the planes written by the step kernel);
+    without sampling, lbm_observables_raw observes the same states in a
+    separate pass.  The time average of five samples (the last one taken when
+    the averages are read) equals the mean of the five separate observations
+    bit for bit, and so does that of seven."""
+    N, K = 19, 3
+    hs = B.lbm_create(N, 1e5, 0.71, cell, storage, B.lbm_default_opts(U=0.1, sample_every=K))
+    hp = B.lbm_create(N, 1e5, 0.71, cell, storage, B.lbm_default_opts(U=0.1))
+    rho, uvwT = synth.rich_fields(N)
+    for h in (hs, hp):
+        B.lbm_set_fields(h, dev(uvwT))
+    acc = np.zeros(B.NRAW)
+    for _ in range(5):
+        B.lbm_step(hs, K)
+        B.lbm_step(hp, K)
+        acc += np.asarray(B.lbm_observables_raw(hp))
+    mean, count = B.lbm_averages(hs)
+    assert count == 5
+    assert np.array_equal(np.asarray(mean), acc / 5), (np.asarray(mean) - acc / 5)
+    # sample states inside and at the end of a step call (t = 18 and 21), the
+    # latter observed by the next call's first step
+    B.lbm_step(hs, 2 * K)
+    B.lbm_step(hs, 1)
+    for _ in range(2):
+        B.lbm_step(hp, K)
+        acc += np.asarray(B.lbm_observables_raw(hp))
+    mean2, count2 = B.lbm_averages(hs)
+    assert count2 == 7
+    assert np.array_equal(np.asarray(mean2), acc / 7)
+
+
 # --------------------------------------------------------------------------
 # Full size, launch configuration of the benchmark
 # --------------------------------------------------------------------------
 
-def test_full_size_257_one_step_against_oracle():
-    """257^3 side-heated, Ra 1e7, FP32 storage and the default launch: the
-    canonical state after 3 steps is handed to the oracle, both take one step,
-    and every population is compared (one FP32 step: tolerance 1e-5)."""
+@pytest.mark.timeout(600)
+def test_full_size_257_even_and_odd_step_against_oracle():
+    """257^3 side-heated, Ra 1e7, FP32 storage and the default launch (the
+    benchmark's kernels): the canonical state after 2 steps is handed to the
+    oracle, then both take one step (the canonical-storage kernel) and one
+    more (the swapped-storage kernel), and every population is compared after
+    each (one FP32 step: tolerance 1e-5)."""
     N = 257
+    say("[257 fp32] GPU: 2 steps, then one even and one odd step")
     h = B.lbm_create(N, 1e7, 0.71, 0, "fp32")
     B.lbm_set_fields(h, dev(synth.rest_with_noise(N)))
-    B.lbm_step(h, 3)
+    B.lbm_step(h, 2)
     before = B.lbm_get_populations(h).cpu().numpy()
     B.lbm_step(h, 1)
-    after = B.lbm_get_populations(h).cpu().numpy()
+    after_even = B.lbm_get_populations(h).cpu().numpy()
+    B.lbm_step(h, 1)
+    after_odd = B.lbm_get_populations(h).cpu().numpy()
     del h
     torch.cuda.empty_cache()
     o = oracle.Oracle(N, 1e7, 0.71, 0)
     o.set_populations(before)
     del before
     o.step(1)
-    assert_pop_close(after, o.pop, o.p, 1e-5, "257^3 one step")
+    assert_pop_close(after_even, o.pop, o.p, 1e-5, "257^3 canonical-storage step")
+    del after_even
+    o.step(1)
+    assert_pop_close(after_odd, o.pop, o.p, 1e-5, "257^3 swapped-storage step")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cell", [0, 1])
+def test_16bit_storages_at_129_against_oracle(cell):
+    """FP16 and FP16C storage at N = 129, where a z-plane (16 641 nodes) spans
+    two sub-blocks of 16 384 nodes, the second one ragged, with 2-byte f slots
+    and 4-byte g slots side by side: from a state exciting every moment, 200
+    steps (canonical storage) and 201 (swapped storage), every population
+    against the oracle at the formats' tolerances."""
+    N = 129
+    o = oracle.Oracle(N, 1e5, 0.71, cell, U=0.1)
+    seed = synth.SEED0 + 100
+    rho, uvwT = synth.rich_fields(N, seed)
+    o.init_fields(uvwT, rho)
+    del rho, uvwT
+    pop = o.pop + 1e-4 * floors(o.p)[:, None] * synth.population_noise(N, seed).reshape(26, -1)
+    o.set_populations(pop)
+    hs = {}
+    for st in ("fp16s", "fp16c"):
+        say(f"[129 {st}] {CELL[cell]}: 200 + 1 steps")
+        hs[st] = B.lbm_create(N, 1e5, 0.71, cell, st, B.lbm_default_opts(U=0.1))
+        B.lbm_set_populations(hs[st], dev(pop))
+        B.lbm_step(hs[st], 200)
+    del pop
+    say(f"[129] oracle 200 steps on {oracle.threads()} threads")
+    o.step(200)
+    for st, h in hs.items():
+        assert_pop_close(B.lbm_get_populations(h).cpu().numpy(), o.pop, o.p, TOL[st],
+                         f"129^3 {st} t=200")
+        B.lbm_step(h, 1)
+    o.step(1)
+    for st, h in hs.items():
+        assert_pop_close(B.lbm_get_populations(h).cpu().numpy(), o.pop, o.p, TOL[st],
+                         f"129^3 {st} t=201 (swapped storage)")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_observables_averages_and_residual_at_65(storage):
+    """N = 65: 17 reduction blocks per plane and 1105 in all, so each block of
+    the first folding level adds several rows.  Rich state, both cells in one
+    handle each; fields, raw observables, the residual over 13 steps and the
+    time averages of five samples taken every 4 steps, against the oracle."""
+    N = 65
+    tol = 1e-11 if storage == "fp64" else 2e-5
+    for cell in (0, 1):
+        pr = Pair(N, 1e5, 0.71, cell, storage, U=0.1, sample_every=4)
+        pr.init_rich()
+        m0 = pr.o.macro()
+        pr.step(13)
+        got = B.lbm_residual(pr.h)
+        want = pr.o.residual(m0)
+        for g, w in zip(got, want):
+            assert abs(g - w) <= (1e-10 if storage == "fp64" else 1e-4) * abs(w), (g, w)
+        mg = B.lbm_get_fields(pr.h).cpu().numpy().reshape(5, -1)
+        mo = pr.o.macro()
+        scale = np.array([1.0, 0.1, 0.1, 0.1, 0.5])[:, None]
+        assert (np.abs(mg - mo) <= tol * np.maximum(np.abs(mo), scale)).all()
+        _raw_close(B.lbm_observables_raw(pr.h), pr.o.observables_raw(), tol * (10 if storage == "fp32" else 1),
+                   _raw_floor(pr.p))
+        B.lbm_reset_averages(pr.h)
+        acc = np.zeros(B.NRAW)
+        for _ in range(5):       # the time 13 + 3 = 16 is the first multiple of 4
+            pr.step(3 if _ == 0 else 4)
+            acc += pr.o.observables_raw()
+        mean, count = B.lbm_averages(pr.h)
+        assert count == 5
+        _raw_close(mean, acc / 5, tol * (10 if storage == "fp32" else 1), _raw_floor(pr.p))
 
 
 @pytest.mark.timeout(900)
@@ -639,20 +762,22 @@ def test_autotune_picks_a_candidate_and_caches_it():
 @pytest.mark.parametrize("storage", ["fp32", "fp16s", "fp16c"])
 def test_checkpoint_restart_continues_bit_for_bit(storage, tmp_path):
     """Save after an odd number of steps (swapped AA parity) with time averages
-    running, load into a fresh handle, and step both: populations and averages
-    agree exactly.  Foreign, mismatched and corrupted files are refused."""
+    running, at a sample state whose sample the step loop has not yet taken
+    (the save takes it), load into a fresh handle, and step both: populations
+    and averages agree exactly.  Foreign, mismatched and corrupted files are
+    refused."""
     N = 13
     say(f"[checkpoint] N={N} storage={storage}")
     opts = B.lbm_default_opts(sample_every=5)
     a = B.lbm_create(N, 1e6, 0.71, "side_heated", storage, opts)
     rho, uvwT = synth.rich_fields(N)
     B.lbm_set_fields(a, dev(uvwT))
-    B.lbm_step(a, 37)
+    B.lbm_step(a, 35)
     path = str(tmp_path / "a.ckpt")
     B.lbm_save(a, path)
     b = B.lbm_create(N, 1e6, 0.71, "side_heated", storage, opts)
     B.lbm_load(b, path)
-    assert B.lbm_time(b) == 37
+    assert B.lbm_time(b) == 35
     B.lbm_step(a, 41)
     B.lbm_step(b, 41)
     pa = B.lbm_get_populations(a).cpu().numpy()
@@ -660,7 +785,7 @@ def test_checkpoint_restart_continues_bit_for_bit(storage, tmp_path):
     assert np.array_equal(pa, pb)
     ra, ca = B.lbm_averages(a)
     rb, cb = B.lbm_averages(b)
-    assert ca == cb == (37 + 41) // 5 and ra == rb
+    assert ca == cb == (35 + 41) // 5 and ra == rb
     assert B.lbm_observables_raw(a) == B.lbm_observables_raw(b)
     # other parameters, other size, corrupted payload, missing file
     c = B.lbm_create(N, 2e6, 0.71, "side_heated", storage, opts)
@@ -753,6 +878,17 @@ def test_small_configuration_steady_state_matches_oracle(storage, floor, rel):
     say(f"[c0 steady {storage}] relative differences " + " ".join(f"{k} {v:+.2e}" for k, v in err.items()))
     for k in keys:
         assert abs(err[k]) <= rel * (2 if k in ("E", "eps_u", "eps_T") else 1), (k, nd[k], no[k], err[k])
+    _check_profile(h, ref, rel, storage)
+
+
+def _check_profile(h, ref, rel, what):
+    """The GPU's Nusselt profile across the cell against the stored oracle
+    profile of the same steady state, plane by plane."""
+    pg = np.asarray(B.lbm_nusselt_profile(h))
+    po = np.asarray(ref["nusselt_profile"])
+    e = np.abs(pg / po - 1.0).max()
+    say(f"[{what}] Nusselt profile: max relative difference {e:.2e}")
+    assert e <= rel, (pg, po)
 
 
 C0_RA1E5_STEADY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c0_ra1e5_steady_oracle.json")
@@ -790,3 +926,46 @@ def test_small_cell_at_ra_1e5_steady_state_matches_oracle(storage, floor, rel):
     say(f"[Ra 1e5 steady {storage}] relative differences " + " ".join(f"{k} {v:+.2e}" for k, v in err.items()))
     for k in keys:
         assert abs(err[k]) <= rel * (2 if k in ("E", "eps_u", "eps_T") else 1), (k, nd[k], no[k], err[k])
+    _check_profile(h, ref, rel, f"Ra 1e5 steady {storage}")
+
+
+RB17_STEADY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rb17_ra1e4_steady_oracle.json")
+
+
+@pytest.mark.parametrize("storage,floor,rel", [("fp64", 1e-11, 1e-8), ("fp32", 1e-6, 3e-4)])
+def test_rayleigh_benard_roll_steady_state_matches_oracle(storage, floor, rel):
+    """The Rayleigh-Benard cube (Sec. 4) at N = 17, Ra 1e4, Pr 0.71, U = 0.1,
+    above onset: from rest + seeded noise a single steady roll, against the
+    oracle's own steady state (tests/golden/rb17_ra1e4_steady_oracle.json,
+    make_c0_steady.py --cell rb --N 17 --Ra 1e4 --tol 1e-11, max |dT| over
+    1000 steps below 1e-11).  FP64 to the oracle's criterion; FP32 for the
+    oracle's steps plus 20 000.  Nu_vol, Nu_kin, Nu_th, the mean of the two
+    walls' Nusselt numbers (the cube keeps an undamped space-time
+    checkerboard of w, so each wall alone alternates by a few 1e-6 from step
+    to step while their mean stays put), Re, the dissipation rates, E and
+    the Nusselt profile."""
+    ref = json.load(open(RB17_STEADY))
+    cfg = ref["config"]
+    h = B.lbm_create(cfg["N"], cfg["Ra"], cfg["Pr"], "rayleigh_benard", storage, B.lbm_default_opts(U=cfg["U"]))
+    B.lbm_set_fields(h, dev(synth.rest_with_noise(cfg["N"], synth.SEED0)))
+    if storage == "fp64":
+        steps, res, _ = B.lbm_run_to_steady(h, 1000, cfg["tol_max_dT_per_1000"], 3 * ref["steps"])
+    else:
+        steps = ref["steps"] + 20_000
+        B.lbm_step(h, steps - 1000)
+        B.lbm_residual(h)
+        B.lbm_step(h, 1000)
+        res = B.lbm_residual(h)[0]
+    nd = B.lbm_nondimensional(B.lbm_get_params(h), B.lbm_observables_raw(h))
+    no = ref["nondimensional"]
+    say(f"[RB17 steady {storage}] {steps} steps, max|dT| {res:.2e} (oracle {ref['steps']} steps)")
+    assert res < floor
+    keys = ("Nu_vol", "Nu_kin", "Nu_th", "Re_rms", "Re_w", "eps_u", "eps_T", "E", "Nu_hot_fd")
+    err = {k: (nd[k] - no[k]) / abs(no[k]) for k in keys}
+    wall_g = 0.5 * (nd["Nu_hot"] + nd["Nu_cold"])
+    wall_o = 0.5 * (no["Nu_hot"] + no["Nu_cold"])
+    err["Nu_wall (mean of the walls)"] = wall_g / wall_o - 1.0
+    say(f"[RB17 steady {storage}] relative differences " + " ".join(f"{k} {v:+.2e}" for k, v in err.items()))
+    for k, v in err.items():
+        assert abs(v) <= rel * (2 if k in ("E", "eps_u", "eps_T") else 1), (k, v)
+    _check_profile(h, ref, rel, f"RB17 steady {storage}")

@@ -1,11 +1,14 @@
 """What the trained warm-start network gains over a start from rest, end to
 end on the GPU at a size that runs in seconds: twelve 17^3 side-heated
-cavities (Ra log-uniform on [1e4, 1e5], Pr 0.71) are advanced to steady
-state in one batch, their fields resampled to 17^3 train the network, and a
-held-out cavity (Ra 3e4, not in the training set) is run to the same steady-
-state criterion from rest and from the network's prediction, plain and
-averaged over the cell's symmetries, and once more in two precision stages
-(FP16C, then FP64) against an FP64 start from rest."""
+cavities (Pr 0.71, six with Ra log-spaced on [1e4, 2e4] and six on
+[5e4, 1e5]) are advanced to steady state in one batch, their fields
+resampled to 17^3 train the network, and a cavity inside the held-out band
+(Ra 3e4, 1.5 to 1.7 times away from the nearest training cavities) is run to
+the same steady-state criterion from rest and from the network's prediction,
+plain and averaged over the cell's symmetries, and once more in two
+precision stages (FP16C, then FP64) against an FP64 start from rest.  The
+warm start must pass the fall-back rule on its own residual, and its gain is
+counted as the strategy's (the probe would be charged had it fallen back)."""
 import numpy as np
 import pytest
 
@@ -42,7 +45,7 @@ def steady_fields(N, M, Ras, Pr, tol):
 def test_warm_start_reaches_steady_state_in_fewer_steps():
     N = M = 17
     Pr = 0.71
-    Ras = list(10 ** np.linspace(4, 5, 12))
+    Ras = list(10 ** np.linspace(4, np.log10(2e4), 6)) + list(10 ** np.linspace(np.log10(5e4), 5, 6))
     fields, sweep_steps = steady_fields(N, M, Ras, Pr, 2e-6)
     say(f"[warm start] training data: 12 cavities steady after <= {sweep_steps} steps")
     cav = [{"N": N, "Ra": r, "Pr": Pr} for r in Ras]
@@ -54,10 +57,14 @@ def test_warm_start_reaches_steady_state_in_fewer_steps():
         r = WS.compare(net, N, 3e4, Pr, storage="fp32", check=500, tol=2e-6, max_steps=200_000, probe=2000,
                        symmetrize=sym, log=lambda s: None)
         say(f"[warm start] symmetrize={sym}: cold {r['cold']['steps']} steps, warm {r['warm']['steps']} steps, "
+            f"strategy {r['strategy_steps']} (kept {r['kept_warm_start']}), "
             f"Nu cold {r['cold']['Nu']['Nu_hot']:.5f} warm {r['warm']['Nu']['Nu_hot']:.5f}")
+        say("[warm start] residuals of the first checks: cold "
+            + " ".join(f"{v:.2e}" for v in r["cold_history_head"][:10]) + " | warm "
+            + " ".join(f"{v:.2e}" for v in r["warm_history_head"][:10]))
         assert r["cold"]["converged"] and r["warm"]["converged"]
         assert r["kept_warm_start"]
-        assert r["warm"]["steps"] <= 0.75 * r["cold"]["steps"]
+        assert r["strategy_steps"] <= 0.75 * r["cold"]["steps"]
         assert abs(r["Nu_rel_diff_warm_vs_cold"]) < 5e-3
     # staged precision: a 16-bit stage to 1e-4, then FP64 to 1e-9, against an
     # FP64 cold start to the same criterion: both reach the same steady state

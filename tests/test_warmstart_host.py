@@ -5,17 +5,32 @@ import math
 import pytest
 
 torch = pytest.importorskip("torch")
-from paper_1903_08882_amd.warmstart import keep_warm_start, merge_stages, steps_to_nu  # noqa: E402
+from paper_1903_08882_amd.warmstart import (keep_warm_start, merge_stages, steps_to_nu,  # noqa: E402
+                                            strategy_cost)
 
 
-def test_fallback_keeps_warm_start_only_when_its_probe_residual_is_lower():
-    assert keep_warm_start((20000, 1e-3), (20000, 1e-2))
-    assert not keep_warm_start((20000, 1e-2), (20000, 1e-3))
-    assert not keep_warm_start((20000, 1e-3), (20000, 1e-3))          # a tie keeps the cold start
-    assert not keep_warm_start(None, (20000, 1e-3))
-    assert not keep_warm_start((20000, math.nan), (20000, 1e-3))       # diverged warm start
-    assert not keep_warm_start((20000, math.inf), (20000, 1e-3))
-    assert keep_warm_start((20000, 1e-3), (20000, math.nan))           # diverged cold start
+def test_fallback_judges_the_warm_run_from_its_own_residual():
+    """The rule sees only the warm run (causal): its residual after the probe
+    (check 20 of 1000 steps each, index 19) against its first check."""
+    decaying = [1e-2 * 0.8 ** j for j in range(40)]            # 1e-2 -> 1.4e-4 at the probe
+    assert keep_warm_start(decaying, 1000, 20_000)
+    assert not keep_warm_start(decaying, 1000, 20_000, decay=100.0)
+    growing = [1e-4 * 1.1 ** j for j in range(40)]              # a start from rest: convection sets in
+    assert not keep_warm_start(growing, 1000, 20_000)
+    flat = [1e-3] * 40
+    assert not keep_warm_start(flat, 1000, 20_000)
+    assert keep_warm_start([1e-3, 1e-5, 1e-7], 1000, 20_000)   # met its tolerance before the probe
+    assert not keep_warm_start([1e-3, math.nan], 1000, 20_000)
+    assert not keep_warm_start([math.inf] + decaying, 1000, 20_000)
+    assert not keep_warm_start(decaying[:19] + [math.nan] + decaying[20:], 1000, 20_000)
+    assert not keep_warm_start([], 1000, 20_000)
+
+
+def test_fallen_back_strategy_pays_the_probe():
+    warm = {"steps": 150_000, "wall_s": 15.0, "probe": (20_000, 3e-3, 2.1)}
+    cold = {"steps": 300_000, "wall_s": 30.0}
+    assert strategy_cost(warm, cold, True) == (150_000, 15.0)
+    assert strategy_cost(warm, cold, False) == (320_000, 32.1)
 
 
 def test_steps_to_nu_counts_from_the_last_entry_into_the_band():
@@ -28,14 +43,14 @@ def test_steps_to_nu_counts_from_the_last_entry_into_the_band():
 
 
 def test_two_stage_record_adds_steps_and_shifts_the_second_nu_track():
-    r1 = {"steps": 68000, "max_dT": 9e-5, "converged": True, "wall_s": 3.0, "probe": (20000, 1e-2),
+    r1 = {"steps": 68000, "max_dT": 9e-5, "converged": True, "wall_s": 3.0, "probe": (20000, 1e-2, 0.9),
           "history": [1e-2, 9e-5], "nu_track": [(20000, 9.0, 8.0), (68000, 8.7, 8.6)]}
-    r2 = {"steps": 210000, "max_dT": 9e-9, "converged": True, "wall_s": 29.0, "probe": (1000, 8e-5),
+    r2 = {"steps": 210000, "max_dT": 9e-9, "converged": True, "wall_s": 29.0, "probe": (1000, 8e-5, 0.1),
           "history": [8e-5, 9e-9], "nu_track": [(10000, 8.671, 8.670), (210000, 8.6708, 8.6708)]}
     r = merge_stages(r1, r2)
     assert r["steps"] == 278000 and r["wall_s"] == 32.0
     assert r["max_dT"] == 9e-9 and r["converged"]
-    assert r["probe"] == (20000, 1e-2)                              # the fall-back rule sees stage 1
+    assert r["probe"] == (20000, 1e-2, 0.9)                         # the fall-back rule sees stage 1
     assert r["stage1"] == {"steps": 68000, "max_dT": 9e-5, "converged": True, "wall_s": 3.0}
     assert r["history"] == [1e-2, 9e-5, 8e-5, 9e-9]
     assert [row[0] for row in r["nu_track"]] == [20000, 68000, 78000, 278000]
