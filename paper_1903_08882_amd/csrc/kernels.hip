@@ -1059,24 +1059,17 @@ __global__ __launch_bounds__(kRedBlock) void k_profile_final(int N, const double
     }
 }
 
-// Reference copy: 16-byte streaming loads and stores, four in flight per
-// thread, a grid-stride loop over n16 16-byte words.
+// Reference copy: one 16-byte streaming load and store per thread over a
+// grid that covers the copy (a grid-stride loop only beyond 2^30 blocks).
+// Of the copy forms measured on MI355X (grid-stride loops with 1-4 words per
+// thread and 2048-16384 blocks, plain or streaming, the runtime's copy) this
+// one moved the most: 6.5 TB/s at 1 GiB against 5.1 for hipMemcpyAsync.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                               uint64_t n16) {
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const u32x4 a = __builtin_nontemporal_load(src + i);
-        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
-        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
-        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + stride);
-        __builtin_nontemporal_store(c, dst + i + 2 * stride);
-        __builtin_nontemporal_store(d, dst + i + 3 * stride);
-    }
-    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 __global__ void k_reset_acc(double *__restrict__ res) {
@@ -1432,11 +1425,8 @@ hipError_t launch_observe(const lbm_t *h, bool accumulate, hipStream_t s) {
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
     const uint64_t n16 = bytes / 16;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const uint64_t want = (n16 + 255) / 256;
-    const uint32_t blocks = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(want, 16ull * cus)));
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, uint64_t{1} << 30));
     k_copy<<<blocks, 256, 0, s>>>(static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n16);
     return hipGetLastError();
 }

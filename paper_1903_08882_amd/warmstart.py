@@ -378,7 +378,7 @@ def _time_at(track, step):
 
 
 def steady_benchmark(N=65, Ra=1e6, Pr=0.71, sweep_K=64, sweep_steps=200_000, iters=1500, holdout=8,
-                     check=1000, nu_every=5000, probe=20_000, decay=10.0, ref_tol=1e-9,
+                     check=1000, nu_every=1000, probe=20_000, decay=10.0, ref_tol=1e-9,
                      max_steps=800_000, seed=synth.SEED0 + 1, log=print):
     """Steps and seconds to a steady side-heated cell, the plain method against
     the learned warm start in 16-bit storage, measured end to end on this GPU:
@@ -415,7 +415,7 @@ def steady_benchmark(N=65, Ra=1e6, Pr=0.71, sweep_K=64, sweep_steps=200_000, ite
     rest = torch.from_numpy(synth.rest_with_noise(N, seed).reshape(-1)).cuda()
     h = B.lbm_create(N, Ra, Pr, "side_heated", "fp64")
     B.lbm_set_fields(h, rest)
-    ref = _track(h, check, ref_tol, 3 * max_steps, 10 * nu_every, log, "fp64 reference")
+    ref = _track(h, check, ref_tol, 3 * max_steps, 10 * check, log, "fp64 reference")
     nu_ref = 0.5 * (ref["nu_track"][-1][1] + ref["nu_track"][-1][2])
     B.lbm_destroy(h)
     out["reference"] = {"storage": "fp64", "tol_max_dT": ref_tol, "steps": ref["steps"],
@@ -436,7 +436,9 @@ def steady_benchmark(N=65, Ra=1e6, Pr=0.71, sweep_K=64, sweep_steps=200_000, ite
                      "seconds_to_tol": round(r["wall_s"], 3) if r["converged"] else None,
                      "final_max_dT": r["max_dT"],
                      "final_Nu_rel_to_ref": (0.5 * (last[1] + last[2]) - nu_ref) / nu_ref,
-                     "history_head": r["history"][:20]}
+                     "residual_at_first_check": r["history"][0] if r["history"] else None,
+                     "residual_at_probe": (r["history"][probe // check - 1]
+                                           if len(r["history"]) >= probe // check else None)}
         if warm:
             keep = keep_warm_start(r["history"], check, probe, decay)
             runs[tag]["kept_by_fallback_rule"] = keep
