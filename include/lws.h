@@ -78,6 +78,23 @@ LBM_API int lws_conv3d_backward_weight(const uint16_t *x, int x_shared, int cin,
                                        int cout, float *dw, lws_grid g, void *work,
                                        size_t work_bytes, void *stream);
 
+/* lws_conv3d_backward_weight for callers that cannot allocate device
+ * memory (code under HIP graph capture, training loops that must not call
+ * hipMalloc): the same arguments without the workspace.  The per-chunk
+ * partial sums go to a 64 MiB device array the library holds on each GPU it
+ * runs on (looked up on the first call made with that device current, kept
+ * until the process ends); the voxel chunks are coarsened where needed so
+ * that every size the original accepts fits in it.  No allocation of any
+ * kind is made.  The result equals lws_conv3d_backward_weight's up to the
+ * rounding of the chunk sums (it is the same where both use the same
+ * chunks).  All calls on one GPU share the array, so calls that overlap on
+ * one GPU (other streams, other threads) race: serialise them.
+ * LBM_EINVAL for bad arguments, LBM_EDEVICE when the array's address cannot
+ * be obtained or a launch fails. */
+LBM_API int lws_conv3d_backward_weight_noalloc(const uint16_t *x, int x_shared, int cin,
+                                               const uint16_t *dz, int cout, float *dw,
+                                               lws_grid g, void *stream);
+
 /* Fields predicted on the node-centred M^3 grid (FP32 channels-last
  * [M^3][ld], channels u/U, v/U, w/U, (T - T_mid)/dT first) interpolated
  * trilinearly onto the N^3 lattice nodes (i + 1/2)/N, in lattice units

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1034,8 +1035,7 @@ hipError_t conv_fwd(const uint16_t *x, int x_shared, int cin, const uint16_t *wp
 }
 
 hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *dz, int cout, float *dw,
-                      const Grid &g, float *work, hipStream_t s) {
-    const uint64_t chunk = wgrad_chunk(g.total, cin);
+                      const Grid &g, float *work, uint64_t chunk, hipStream_t s) {
     const unsigned nchunks = static_cast<unsigned>((g.total + chunk - 1) / chunk);
     const int mrows = 27 * cin;
     if (cin % 8 == 0 && cout % 8 == 0 && g.total + chunk < (uint64_t{1} << 32)) {   // 32-bit voxel indices
@@ -1074,10 +1074,55 @@ hipError_t conv_wgrad(const uint16_t *x, int x_shared, int cin, const uint16_t *
     return hipGetLastError();
 }
 
-size_t wgrad_work(int cin, int cout, const Grid &g) {
-    const uint64_t chunk = wgrad_chunk(g.total, cin);
+size_t wgrad_work_for(int cin, int cout, const Grid &g, uint64_t chunk) {
     const uint64_t nchunks = (g.total + chunk - 1) / chunk;
     return static_cast<size_t>(nchunks) * 27 * cin * cout * sizeof(float);
+}
+
+size_t wgrad_work(int cin, int cout, const Grid &g) {
+    return wgrad_work_for(cin, cout, g, wgrad_chunk(g.total, cin));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free weight gradient: its per-chunk partial tiles go to this
+// file-scope device array instead of a caller's workspace.  Each GPU the
+// library runs on holds its own copy (until the process ends); host code
+// uses the address hipGetSymbolAddress gives on that device, never the
+// array's name.  Every call overwrites the partials it reads, so nothing is
+// cleared; calls that overlap on one GPU race for it.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t{64} << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+hipError_t scratch_on_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+// Voxels per chunk when the partials must fit in the scratch array: the
+// usual chunking, coarsened until the chunk tiles fit.
+uint64_t wgrad_chunk_capped(uint64_t total, int cin, int cout) {
+    const uint64_t tile = static_cast<uint64_t>(27) * cin * cout * sizeof(float);
+    const uint64_t maxchunks = std::max<uint64_t>(1, kScratchBytes / tile);
+    uint64_t c = std::max(wgrad_chunk(total, cin), (total + maxchunks - 1) / maxchunks);
+    return (c + kWgVox - 1) / kWgVox * kWgVox;
 }
 
 hipError_t pack(const float *w, int cin, int cout, int dgrad, uint16_t *out, hipStream_t s) {
@@ -1232,7 +1277,9 @@ hipError_t layer_bwd(lws_net_t *n, int l, const float *da, int dstride, int doff
     k_film_grads<<<1, 64, 0, s>>>(n->fsum, B, y.cout, n->cond, gp(n, y.oGw), gp(n, y.oGb), gp(n, y.oBw),
                                   gp(n, y.oBb));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = conv_wgrad(x, x_shared, y.cin, n->dzb, y.cout, gp(n, y.oW), g, n->work, s)) != hipSuccess) return e;
+    if ((e = conv_wgrad(x, x_shared, y.cin, n->dzb, y.cout, gp(n, y.oW), g, n->work,
+                        wgrad_chunk(g.total, y.cin), s)) != hipSuccess)
+        return e;
     if (dx) e = conv_fwd(n->dzb, 0, y.cout, n->packed + y.pd, y.kpd, y.cin, dx, g, s);
     return e;
 }
@@ -1298,7 +1345,9 @@ hipError_t backward(lws_net_t *n, int B, hipStream_t s) {
     const Layer &o = n->L[OUT];
     const Grid g0 = make_grid(level_grid(n, B, 0));
     // output layer: weights, bias, input gradient
-    if ((e = conv_wgrad(n->aD1, 0, o.cin, n->doutb, o.cout, gp(n, o.oW), g0, n->work, s)) != hipSuccess) return e;
+    if ((e = conv_wgrad(n->aD1, 0, o.cin, n->doutb, o.cout, gp(n, o.oW), g0, n->work,
+                        wgrad_chunk(g0.total, o.cin), s)) != hipSuccess)
+        return e;
     // bias gradient: enough blocks to stream dout at full rate (64 blocks ran
     // at ~0.2 TB/s), within the partial buffer
     const size_t part_cap = static_cast<size_t>(n->maxB) * n->nbx * 2 * 64 + 4096;
@@ -1381,7 +1430,22 @@ int lws_conv3d_backward_weight(const uint16_t *x, int x_shared, int cin, const u
         return LBM_EINVAL;
     const Grid gg = make_grid(g);
     if (work_bytes < wgrad_work(cin, cout, gg)) return LBM_ENOMEM;
-    return conv_wgrad(x, x_shared, cin, dz, cout, dw, gg, static_cast<float *>(work),
+    return conv_wgrad(x, x_shared, cin, dz, cout, dw, gg, static_cast<float *>(work), wgrad_chunk(gg.total, cin),
+                      static_cast<hipStream_t>(stream)) == hipSuccess
+               ? LBM_OK
+               : LBM_EDEVICE;
+}
+
+int lws_conv3d_backward_weight_noalloc(const uint16_t *x, int x_shared, int cin, const uint16_t *dz, int cout,
+                                       float *dw, lws_grid g, void *stream) {
+    if (!x || !dz || !dw || !grid_ok(g) || cin < 1 || cin > kMaxCin || cout < 1 || cout > kMaxCout)
+        return LBM_EINVAL;
+    const Grid gg = make_grid(g);
+    const uint64_t chunk = wgrad_chunk_capped(gg.total, cin, cout);
+    if (wgrad_work_for(cin, cout, gg, chunk) > kScratchBytes) return LBM_EINVAL;   // cannot fit
+    void *ptr = nullptr;
+    if (scratch_on_current_device(&ptr) != hipSuccess) return LBM_EDEVICE;
+    return conv_wgrad(x, x_shared, cin, dz, cout, dw, gg, static_cast<float *>(ptr), chunk,
                       static_cast<hipStream_t>(stream)) == hipSuccess
                ? LBM_OK
                : LBM_EDEVICE;

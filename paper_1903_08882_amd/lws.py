@@ -27,6 +27,8 @@ _SIG = {
     "lws_wgrad_work_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, lws_grid]),
     "lws_conv3d_backward_weight": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P,
                                                   lws_grid, _P, ctypes.c_size_t, _P]),
+    "lws_conv3d_backward_weight_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
+                                                          _P, lws_grid, _P]),
     "lws_upsample_fields": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            _P, _P]),
@@ -126,6 +128,18 @@ def lws_conv3d_backward_weight(x, x_shared, cin, dz, cout, grid, out=None, work=
                                             _ptr(out, torch.float32, 27 * cin * cout), _grid(grid),
                                             _ptr(work, torch.uint8, wb), ctypes.c_size_t(work.numel()),
                                             _stream(stream)))
+    return out
+
+
+def lws_conv3d_backward_weight_noalloc(x, x_shared, cin, dz, cout, grid, out, stream=None):
+    """As lws_conv3d_backward_weight with the library's own scratch array
+    instead of a workspace; out must be given (nothing is allocated)."""
+    V = _vox(grid)
+    nx = (V // int(grid[0]) if x_shared else V) * cin
+    _check(lib().lws_conv3d_backward_weight_noalloc(_ptr(x, torch.int16, nx), int(bool(x_shared)), int(cin),
+                                                    _ptr(dz, torch.int16, V * cout), int(cout),
+                                                    _ptr(out, torch.float32, 27 * cin * cout), _grid(grid),
+                                                    _stream(stream)))
     return out
 
 
