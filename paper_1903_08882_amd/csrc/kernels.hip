@@ -539,6 +539,7 @@ template <class R>
 __device__ __forceinline__ void write_planes(const ObsOut<R> &o, const Geo &g, const Node &d,
                                              const Macro<R> &m) {
     const uint64_t V = static_cast<uint64_t>(g.N2) * g.N;
+    // plain stores: streaming ones cost the 257^3 FP32 sample step 33 us more
     o.planes[d.n] = m.drho;
     o.planes[V + d.n] = m.ux;
     o.planes[2 * V + d.n] = m.uy;
@@ -782,127 +783,150 @@ __device__ __forceinline__ void block_reduce_to(double (&v)[K], double *__restri
 // central inside; at the first node next to a wall the quadratic through the
 // wall value (w_lo or w_hi) half a cell away and the two nearest nodes, or
 // with a mirror node (dphi/dn = 0) at an adiabatic wall.
-__device__ __forceinline__ double dfd(double lo, double c, double hi, int k, int N, double w_lo,
-                                      double w_hi, bool mirror) {
-    if (k > 0 && k < N - 1) return 0.5 * (hi - lo);
-    if (k == 0) return mirror ? 0.5 * (hi - c) : (-4.0 / 3.0) * w_lo + c + hi * (1.0 / 3.0);
-    return mirror ? 0.5 * (c - lo) : (4.0 / 3.0) * w_hi - c - lo * (1.0 / 3.0);
+template <class A>
+__device__ __forceinline__ A dfd(A lo, A c, A hi, int k, int N, A w_lo, A w_hi, bool mirror) {
+    if (k > 0 && k < N - 1) return A(0.5) * (hi - lo);
+    if (k == 0) return mirror ? A(0.5) * (hi - c) : A(-4.0 / 3.0) * w_lo + c + hi * A(1.0 / 3.0);
+    return mirror ? A(0.5) * (c - lo) : A(4.0 / 3.0) * w_hi - c - lo * A(1.0 / 3.0);
 }
 
 struct ObsArgs {
     double nu, kappa, T_hot, T_cold;
 };
 
-// z-planes per block of the observable reduction.
+// z-planes per block of the observable reduction, and the in-plane nodes a
+// block adds up (62 of the 64 lanes of each of its 4 waves).
 constexpr int kObsZ = 16;
+constexpr int kObsTile = 4 * 62;
 
 // Observable partial sums from the observation planes [rho - 1, u, v, w, T]
-// (type P) and the wall flux (NULL before the first step).  A block takes 256
-// consecutive in-plane nodes r and marches them through kObsZ planes: the
-// values at z - 1, z and z + 1 stay in registers, the in-plane neighbours
-// r +- 1 and r +- N are read from the lines the block and its neighbours load
-// at the same time, so each plane value comes from HBM once.  Logical block
-// lb = chunk * ntile + tile; every block writes one row of partials.
-template <int CELL, class P>
+// (type P; the differences and products are formed in P, each node's terms
+// added to FP64 sums) and the wall flux (NULL before the first step).  A
+// block takes kObsTile consecutive in-plane nodes r and marches them through
+// ZC planes: the values at z - 1, z and z + 1 stay in registers, the
+// neighbours r +- 1 come from the neighbouring lanes (each wave's outer lanes
+// hold them), r +- N from the lines the block and its neighbours load at the
+// same time, so each plane value comes from HBM about once.  Logical block
+// lb = chunk * ntile + tile; every block writes one row of partials.  At
+// 257^3 in FP32: 206 us (from 618 us with a lane per node, edge loads and FP64
+// differences; 665 us for the earlier pass over FP64 planes).
+template <int CELL, class P, int ZC = kObsZ>
 __global__ __launch_bounds__(kRedBlock) void k_observe(int N, uint32_t ntile, ObsArgs a,
                                                        const P *__restrict__ pl,
                                                        const double *__restrict__ wall,
                                                        double *__restrict__ part) {
     const uint32_t lb = xcd_order();
     const uint32_t tile = lb % ntile, chunk = lb / ntile;
-    const uint32_t N2 = static_cast<uint32_t>(N) * N;
-    const uint32_t r = tile * kRedBlock + threadIdx.x;
+    const int N2 = N * N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the first and last lane of each wave only carry the values of the
+    // neighbours r - 1 and r + 1 of the 62 lanes between them
+    const int ri = static_cast<int>(tile) * kObsTile + wave * 62 + lane - 1;
+    const bool has = ri >= 0 && ri < N2;                  // a node whose values this lane loads
+    const bool live = has && lane >= 1 && lane <= 62;     // ... and whose terms it adds
     double v[LBM_NRAW];
 #pragma unroll
     for (int k = 0; k < LBM_NRAW; ++k) v[k] = 0.0;
-    if (r < N2) {
-        const uint64_t V = static_cast<uint64_t>(N2) * N;
-        const P *D = pl, *F[4] = {pl + V, pl + 2 * V, pl + 3 * V, pl + 4 * V};   // u, v, w, T
-        const int y = static_cast<int>(r / N), x = static_cast<int>(r) - y * N;
-        const int z0 = static_cast<int>(chunk) * kObsZ, z1 = min(N, z0 + kObsZ);
-        constexpr int iso = CELL == LBM_SIDE_HEATED ? 0 : 2;
-        const int mid_lo = (N - 1) / 2, mid_hi = N / 2;
-        const double wm = (y == mid_lo || y == mid_hi) ? (mid_lo == mid_hi ? 1.0 : 0.5) : 0.0;
-        double lo[4], c[4], hi[4];   // (u, v, w, T) at z - 1, z, z + 1
-        {
-            const uint64_t n = r + static_cast<uint64_t>(z0) * N2;
+    const uint64_t V = static_cast<uint64_t>(N2) * N;
+    const P *D = pl, *F[4] = {pl + V, pl + 2 * V, pl + 3 * V, pl + 4 * V};   // u, v, w, T
+    const int y = has ? ri / N : 0, x = has ? ri - y * N : 0;
+    const int z0 = static_cast<int>(chunk) * ZC, z1 = min(N, z0 + ZC);
+    constexpr int iso = CELL == LBM_SIDE_HEATED ? 0 : 2;
+    const int mid_lo = (N - 1) / 2, mid_hi = N / 2;
+    const double wm = (y == mid_lo || y == mid_hi) ? (mid_lo == mid_hi ? 1.0 : 0.5) : 0.0;
+    const P nu = static_cast<P>(a.nu), kappa = static_cast<P>(a.kappa);
+    const P Th = static_cast<P>(a.T_hot), Tc = static_cast<P>(a.T_cold);
+    // (u, v, w, T) at z - 1, z, z + 1 and at y -+ 1 of plane z; the loads for
+    // plane z + 1 are issued before plane z is worked on, so their latency
+    // overlaps the arithmetic
+    P lo[4], c[4], hi[4], yl[4], yh[4];
+    {
+        const P *p0[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                c[q] = static_cast<double>(F[q][n]);
-                lo[q] = z0 > 0 ? static_cast<double>(F[q][n - N2]) : 0.0;
-            }
+        for (int q = 0; q < 4; ++q) {
+            p0[q] = F[q] + static_cast<uint64_t>(z0) * N2;
+            c[q] = has ? p0[q][ri] : P(0);
+            lo[q] = has && z0 > 0 ? p0[q][ri - N2] : P(0);
+            hi[q] = has && z0 + 1 < N ? p0[q][ri + N2] : P(0);
+            yl[q] = live && y > 0 ? p0[q][ri - N] : P(0);
+            yh[q] = live && y < N - 1 ? p0[q][ri + N] : P(0);
         }
-        for (int z = z0; z < z1; ++z) {
-            const uint64_t n = r + static_cast<uint64_t>(z) * N2;
+    }
+#pragma unroll 1
+    for (int z = z0; z < z1; ++z) {
+        P nhi[4], nyl[4], nyh[4], xl[4], xh[4];
+        const bool more = z + 1 < z1;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) hi[q] = z + 1 < N ? static_cast<double>(F[q][n + N2]) : 0.0;
-            double xl[4], xh[4], yl[4], yh[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                xl[q] = x > 0 ? static_cast<double>(F[q][n - 1]) : 0.0;
-                xh[q] = x < N - 1 ? static_cast<double>(F[q][n + 1]) : 0.0;
-                yl[q] = y > 0 ? static_cast<double>(F[q][n - N]) : 0.0;
-                yh[q] = y < N - 1 ? static_cast<double>(F[q][n + N]) : 0.0;
-            }
-            const int c3[3] = {x, y, z};
-            double du[3][3];   // du[i][j] = d_i u_j
+        for (int q = 0; q < 4; ++q) {
+            const P *p1 = F[q] + static_cast<uint64_t>(z + 1) * N2;
+            nhi[q] = more && has && z + 2 < N ? p1[ri + N2] : P(0);
+            nyl[q] = more && live && y > 0 ? p1[ri - N] : P(0);
+            nyh[q] = more && live && y < N - 1 ? p1[ri + N] : P(0);
+            // r - 1 and r + 1 are the neighbouring lanes' own values
+            xl[q] = __shfl_up(c[q], 1, 64);
+            xh[q] = __shfl_down(c[q], 1, 64);
+        }
+        if (live) {
+            P du[3][3];   // du[i][j] = d_i u_j
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                du[0][j] = dfd(xl[j], c[j], xh[j], x, N, 0.0, 0.0, false);
-                du[1][j] = dfd(yl[j], c[j], yh[j], y, N, 0.0, 0.0, false);
-                du[2][j] = dfd(lo[j], c[j], hi[j], z, N, 0.0, 0.0, false);
+                du[0][j] = dfd<P>(xl[j], c[j], xh[j], x, N, P(0), P(0), false);
+                du[1][j] = dfd<P>(yl[j], c[j], yh[j], y, N, P(0), P(0), false);
+                du[2][j] = dfd<P>(lo[j], c[j], hi[j], z, N, P(0), P(0), false);
             }
-            const double dT[3] = {dfd(xl[3], c[3], xh[3], x, N, a.T_hot, a.T_cold, iso != 0),
-                                  dfd(yl[3], c[3], yh[3], y, N, a.T_hot, a.T_cold, true),
-                                  dfd(lo[3], c[3], hi[3], z, N, a.T_hot, a.T_cold, iso != 2)};
-            double eu = 0.0;
+            const P dT[3] = {dfd<P>(xl[3], c[3], xh[3], x, N, Th, Tc, iso != 0),
+                             dfd<P>(yl[3], c[3], yh[3], y, N, Th, Tc, true),
+                             dfd<P>(lo[3], c[3], hi[3], z, N, Th, Tc, iso != 2)};
+            P eu = P(0);
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const double sij = du[i][j] + du[j][i];
+                    const P sij = du[i][j] + du[j][i];
                     eu += sij * sij;
                 }
-            const double u = c[0], vv = c[1], w = c[2], Tn = c[3];
-            const double dr = static_cast<double>(D[n]);
-            const double div = du[0][0] + du[1][1] + du[2][2];
-            v[LBM_RAW_U2] += u * u + vv * vv + w * w;
-            v[LBM_RAW_W2] += w * w;
-            v[LBM_RAW_WT] += w * Tn;
-            v[LBM_RAW_UT] += u * Tn;
-            v[LBM_RAW_EPS_U] += 0.5 * a.nu * eu;
-            v[LBM_RAW_EPS_T] += a.kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
-            v[LBM_RAW_DRHO2] += dr * dr;
-            v[LBM_RAW_T] += Tn;
-            v[LBM_RAW_DRHO] += dr;
-            v[LBM_RAW_DIV2] += div * div;
-            const int k = c3[iso];
-            const double T_in = iso == 0 ? (k == 0 ? xh[3] : xl[3]) : (k == 0 ? hi[3] : lo[3]);
-            const uint64_t w2 = CELL == LBM_SIDE_HEATED ? y + static_cast<uint64_t>(N) * z
-                                                        : x + static_cast<uint64_t>(N) * y;
-            if (k == 0) {
-                const double q = wall ? wall[w2] : 0.0;
-                const double gr = -(-8.0 * a.T_hot + 9.0 * Tn - T_in) * (1.0 / 3.0);
-                v[LBM_RAW_FLUX_HOT] += q;
-                v[LBM_RAW_FLUX_HOT_MID] += wm * q;
-                v[LBM_RAW_GRAD_HOT] += gr;
-                v[LBM_RAW_GRAD_HOT_MID] += wm * gr;
-            }
-            if (k == N - 1) {
-                const double q = wall ? wall[N2 + w2] : 0.0;
-                const double gr = (8.0 * a.T_cold - 9.0 * Tn + T_in) * (1.0 / 3.0);
-                v[LBM_RAW_FLUX_COLD] += q;
-                v[LBM_RAW_FLUX_COLD_MID] += wm * q;
-                v[LBM_RAW_GRAD_COLD] += gr;
-                v[LBM_RAW_GRAD_COLD_MID] += wm * gr;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                lo[q] = c[q];
-                c[q] = hi[q];
+            const P u = c[0], vv = c[1], w = c[2], Tn = c[3];
+            const P dr = (D + static_cast<uint64_t>(z) * N2)[ri];
+            const P div = du[0][0] + du[1][1] + du[2][2];
+            v[LBM_RAW_U2] += static_cast<double>(u * u + vv * vv + w * w);
+            v[LBM_RAW_W2] += static_cast<double>(w * w);
+            v[LBM_RAW_WT] += static_cast<double>(w * Tn);
+            v[LBM_RAW_UT] += static_cast<double>(u * Tn);
+            v[LBM_RAW_EPS_U] += static_cast<double>(P(0.5) * nu * eu);
+            v[LBM_RAW_EPS_T] += static_cast<double>(kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]));
+            v[LBM_RAW_DRHO2] += static_cast<double>(dr * dr);
+            v[LBM_RAW_T] += static_cast<double>(Tn);
+            v[LBM_RAW_DRHO] += static_cast<double>(dr);
+            v[LBM_RAW_DIV2] += static_cast<double>(div * div);
+            const int k = iso == 0 ? x : z;
+            if (k == 0 || k == N - 1) {
+                const P T_in = iso == 0 ? (k == 0 ? xh[3] : xl[3]) : (k == 0 ? hi[3] : lo[3]);
+                const uint64_t w2 = CELL == LBM_SIDE_HEATED ? y + static_cast<uint64_t>(N) * z
+                                                            : x + static_cast<uint64_t>(N) * y;
+                if (k == 0) {
+                    v[LBM_RAW_FLUX_HOT] += wall ? wall[w2] : 0.0;
+                    v[LBM_RAW_GRAD_HOT] += static_cast<double>(-(P(-8) * Th + P(9) * Tn - T_in) * P(1.0 / 3.0));
+                } else {
+                    v[LBM_RAW_FLUX_COLD] += wall ? wall[N2 + w2] : 0.0;
+                    v[LBM_RAW_GRAD_COLD] += static_cast<double>((P(8) * Tc - P(9) * Tn + T_in) * P(1.0 / 3.0));
+                }
             }
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lo[q] = c[q];
+            c[q] = hi[q];
+            hi[q] = nhi[q];
+            yl[q] = nyl[q];
+            yh[q] = nyh[q];
+        }
     }
+    // the mid-line weight depends on y only, which a thread keeps (0, 1/2 or
+    // 1: the scaling is exact)
+    v[LBM_RAW_FLUX_HOT_MID] = wm * v[LBM_RAW_FLUX_HOT];
+    v[LBM_RAW_GRAD_HOT_MID] = wm * v[LBM_RAW_GRAD_HOT];
+    v[LBM_RAW_FLUX_COLD_MID] = wm * v[LBM_RAW_FLUX_COLD];
+    v[LBM_RAW_GRAD_COLD_MID] = wm * v[LBM_RAW_GRAD_COLD];
     block_reduce_to<LBM_NRAW, false>(v, part + static_cast<uint64_t>(lb) * kNPart);
 }
 
@@ -1388,7 +1412,7 @@ hipError_t launch_obs_planes(const lbm_t *h, hipStream_t s) {
     });
 }
 
-uint32_t observe_tiles(int N) { return (static_cast<uint32_t>(N) * N + kRedBlock - 1) / kRedBlock; }
+uint32_t observe_tiles(int N) { return (static_cast<uint32_t>(N) * N + kObsTile - 1) / kObsTile; }
 uint32_t observe_blocks(int N) { return observe_tiles(N) * ((N + kObsZ - 1) / kObsZ); }
 
 hipError_t launch_observe_reduce(const lbm_t *h, bool accumulate, hipStream_t s) {

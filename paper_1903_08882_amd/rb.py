@@ -9,7 +9,10 @@ transient of at least `--min-transient` free-fall times, run in blocks of
 blocks differ by less than `--settle` (relative), then `--avg-steps` steps of
 averaging split into `--sub` equal sub-blocks, the observables sampled every
 `--sample-every` steps and accumulated in FP64 on the GPU.  Reports the means,
-the standard error of the sub-block means, and the paper's values for the same
+the standard error of the sub-block means (or, with `--batches`, of the means of
+that many runs of consecutive sub-blocks, which are less correlated than single
+short sub-blocks), optionally the same over the first `--prefix-steps` averaging
+steps, and the paper's values for the same
 (Ra, Pr) as context (the paper's grids and averaging times differ).  One JSON
 line per storage format, then a comparison line when there are several.
 """
@@ -57,8 +60,25 @@ def standard_errors(subs, keys):
     return out
 
 
+def _mean_raw(raws):
+    return [sum(r[j] for r in raws) / len(raws) for j in range(len(raws[0]))]
+
+
+def batch_means(params, raws, batches):
+    """Group equal sub-blocks into `batches` runs of consecutive sub-blocks
+    and summarise each run from its mean raw sums (the observables are ratios
+    of the sums, so a run's value comes from its sums, not from averaging the
+    sub-block ratios).  The count of sub-blocks must be a multiple of
+    `batches`."""
+    if batches <= 0 or len(raws) % batches:
+        raise ValueError(f"{len(raws)} sub-blocks do not split into {batches} batches")
+    g = len(raws) // batches
+    return [_summary(params, _mean_raw(raws[i * g:(i + 1) * g])) for i in range(batches)]
+
+
 def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, settle=0.01,
-             max_transient_tf=400.0, avg_steps=100_000, sub=10, sample_every=100, log=print):
+             max_transient_tf=400.0, avg_steps=100_000, sub=10, sample_every=100, log=print,
+             batches=None, prefix_steps=None):
     opts = B.lbm_default_opts(sample_every=sample_every)
     h = B.lbm_create(N, Ra, Pr, "rayleigh_benard", storage, opts)
     p = B.lbm_get_params(h)
@@ -66,7 +86,7 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
     blk = max(sample_every, int(round(block_tf * tf / sample_every)) * sample_every)
     B.lbm_set_fields(h, torch.from_numpy(synth.rest_with_noise(N, seed).reshape(-1)).cuda())
     t0 = time.perf_counter()
-    steps, prev, trans = 0, None, []
+    steps, prev, trans, settled = 0, None, [], False
     while True:
         B.lbm_reset_averages(h)
         B.lbm_step(h, blk)
@@ -81,6 +101,7 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
             f"(change {d:.2%})  {time.perf_counter() - t0:.0f} s")
         prev = nu
         if steps >= min_transient_tf * tf and d < settle:
+            settled = True
             break
         if steps >= max_transient_tf * tf:
             log(f"# {storage}: block means still moving after {max_transient_tf:.0f} t_f")
@@ -99,15 +120,24 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
             f"Re_rms {subs[-1]['Re_rms']:.2f}  {time.perf_counter() - t0:.0f} s")
     torch.cuda.synchronize()
     wall_avg = time.perf_counter() - ta
-    mean_raw = [sum(r[j] for r in raws) / sub for j in range(len(raws[0]))]
-    mean = _summary(p, mean_raw)
-    se = standard_errors(subs, KEYS)
+    mean = _summary(p, _mean_raw(raws))
+    se = standard_errors(batch_means(p, raws, batches) if batches else subs, KEYS)
     out = {"N": N, "Ra": Ra, "Pr": Pr, "storage": storage, "seed": seed,
            "steps_per_tf": tf, "transient_steps": transient, "transient_block_Nu_vol": trans,
+           "settled": settled,
            "avg_steps": per * sub, "avg_tf": per * sub / tf, "samples": per * sub // sample_every,
+           "stderr_over": f"{batches or sub} batches of {sub // (batches or sub)} sub-blocks",
            "mean": mean, "stderr": se,
            "MLUPS_averaging": N ** 3 * per * sub / wall_avg / 1e6,
            "wall_s": time.perf_counter() - t0}
+    if prefix_steps:
+        k = prefix_steps // per
+        if k < 2 or k * per != prefix_steps or k > sub:
+            raise ValueError(f"prefix of {prefix_steps} steps is not 2..{sub} sub-blocks of {per}")
+        out["prefix"] = {"avg_steps": k * per, "avg_tf": k * per / tf,
+                         "mean": _summary(p, _mean_raw(raws[:k])),
+                         "stderr": standard_errors(subs[:k], KEYS),
+                         "stderr_over": f"{k} sub-blocks"}
     ref = PAPER.get((Ra, Pr))
     if ref:
         out["paper"] = dict(zip(KEYS[:6], ref))
@@ -131,6 +161,12 @@ def main():
     ap.add_argument("--avg-steps", type=int, default=100_000)
     ap.add_argument("--sub", type=int, default=10)
     ap.add_argument("--sample-every", type=int, default=100)
+    ap.add_argument("--batches", type=int, default=None,
+                    help="standard errors over this many runs of consecutive sub-blocks "
+                         "(default: over the sub-blocks themselves)")
+    ap.add_argument("--prefix-steps", type=int, default=None,
+                    help="also report the mean and standard error over the first this many "
+                         "averaging steps (a whole number of sub-blocks)")
     a = ap.parse_args()
     cases = [(1e6, 0.7), (3e6, 0.7), (1e7, 0.7), (1e6, 7.0), (3e6, 7.0), (1e7, 7.0)]
     seed = a.seed
@@ -141,18 +177,30 @@ def main():
     for s in a.storage:
         r = run_case(a.N, a.Ra, a.Pr, s, seed, a.min_transient, a.block_tf, a.settle,
                      a.max_transient, a.avg_steps, a.sub, a.sample_every,
-                     log=lambda m: print(m, flush=True))
+                     log=lambda m: print(m, flush=True), batches=a.batches,
+                     prefix_steps=a.prefix_steps)
         res.append(r)
         print(json.dumps(r), flush=True)
     if len(res) > 1:
         base = res[0]
-        cmp = {}
-        for r in res[1:]:
-            cmp[r["storage"]] = {
-                k: {"rel_diff": (r["mean"][k] - base["mean"][k]) / base["mean"][k],
-                    "combined_stderr_rel": math.hypot(r["stderr"][k], base["stderr"][k])
-                    / abs(base["mean"][k])} for k in KEYS[:8]}
-        print(json.dumps({"compare_against": base["storage"], "diff": cmp}), flush=True)
+        print(json.dumps({"compare_against": base["storage"], "diff": compare(base, res[1:])}),
+              flush=True)
+        if a.prefix_steps:
+            print(json.dumps({"compare_against": base["storage"], "over": "prefix",
+                              "diff": compare(base["prefix"], [r["prefix"] | {"storage": r["storage"]}
+                                                               for r in res[1:]])}), flush=True)
+
+
+def compare(base, others):
+    """Relative difference of each mean from `base`'s, with the two standard
+    errors combined in quadrature relative to `base`'s mean."""
+    cmp = {}
+    for r in others:
+        cmp[r["storage"]] = {
+            k: {"rel_diff": (r["mean"][k] - base["mean"][k]) / base["mean"][k],
+                "combined_stderr_rel": math.hypot(r["stderr"][k], base["stderr"][k])
+                / abs(base["mean"][k])} for k in KEYS[:8]}
+    return cmp
 
 
 if __name__ == "__main__":
