@@ -799,6 +799,150 @@ struct ObsArgs {
 constexpr int kObsZ = 16;
 constexpr int kObsTile = 4 * 62;
 
+// The value held by lane - 1 (from_left) or lane + 1 (from_right) of the
+// wave: a DPP move across the whole 64-lane wave, no LDS traffic.  Lanes 0
+// and 63 receive 0 (they are halo lanes whose terms are not added).
+__device__ __forceinline__ int dpp_from_left(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_from_right(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+template <class P>
+__device__ __forceinline__ P from_left(P v) {
+    if constexpr (sizeof(P) == 4) {
+        return __int_as_float(dpp_from_left(__float_as_int(v)));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const uint32_t lo = static_cast<uint32_t>(dpp_from_left(static_cast<int>(b)));
+        const long long hi = dpp_from_left(static_cast<int>(b >> 32));
+        return __longlong_as_double((hi << 32) | lo);
+    }
+}
+template <class P>
+__device__ __forceinline__ P from_right(P v) {
+    if constexpr (sizeof(P) == 4) {
+        return __int_as_float(dpp_from_right(__float_as_int(v)));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const uint32_t lo = static_cast<uint32_t>(dpp_from_right(static_cast<int>(b)));
+        const long long hi = dpp_from_right(static_cast<int>(b >> 32));
+        return __longlong_as_double((hi << 32) | lo);
+    }
+}
+
+// What a lane of the observable reduction holds of one plane z: (u, v, w, T)
+// at its node and at y -+ 1, rho - 1, and (side-heated cell) the two wall
+// fluxes of its row (y, z).
+template <int CELL, class P>
+struct ObsPlane {
+    P c[4], yl[4], yh[4], d;
+    double wh, wc;
+};
+
+// Loads of plane zc for in-plane node rc (rows ryl, ryh for y -+ 1), every one
+// issued by every lane at an address clamped into the arrays: a load under a
+// branch would make the compiler wait for all loads in flight before its value
+// is used, which serialises the planes.  Values at clamped addresses are not
+// used.  wsrc: the wall fluxes, or (before the first step) any array of at
+// least 2 N^2 doubles, whose values are then discarded.
+template <int CELL, class P>
+__device__ __forceinline__ void obs_load(ObsPlane<CELL, P> &o, const P *const (&F)[4],
+                                         const P *D, const double *wsrc, int zc, int N, int N2,
+                                         int rc, int ryl, int ryh) {
+    const uint64_t zo = static_cast<uint64_t>(zc) * N2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        o.c[q] = F[q][zo + rc];
+        o.yl[q] = F[q][zo + ryl];
+        o.yh[q] = F[q][zo + ryh];
+    }
+    o.d = D[zo + rc];
+    if constexpr (CELL == LBM_SIDE_HEATED) {
+        const uint64_t w = rc / N + static_cast<uint64_t>(N) * zc;   // y + N z
+        o.wh = wsrc[w];
+        o.wc = wsrc[static_cast<uint64_t>(N2) + w];
+    }
+}
+
+// A node's terms of plane z, added to the FP64 sums v: lo = (u, v, w, T) at
+// z - 1, cur = plane z, hi = (u, v, w, T) at z + 1.  The differences and
+// products are formed in P.  Where a neighbour would lie outside the cell its
+// value is not used (dfd takes the wall formula there).
+template <int CELL, class P>
+__device__ __forceinline__ void obs_terms(double (&v)[LBM_NRAW], const P (&lo)[4],
+                                          const ObsPlane<CELL, P> &cur, const P (&hi)[4],
+                                          int x, int y, int z, int N, int N2, bool live,
+                                          const double *wall, const ObsArgs &a) {
+    constexpr int iso = CELL == LBM_SIDE_HEATED ? 0 : 2;
+    const P nu = static_cast<P>(a.nu), kappa = static_cast<P>(a.kappa);
+    const P Th = static_cast<P>(a.T_hot), Tc = static_cast<P>(a.T_cold);
+    // r - 1 and r + 1 are the neighbouring lanes' own values (every lane
+    // takes part in the moves)
+    P xl[4], xh[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        xl[q] = from_left(cur.c[q]);
+        xh[q] = from_right(cur.c[q]);
+    }
+    if (!live) return;
+    const P *c = cur.c, *yl = cur.yl, *yh = cur.yh;
+    P du[3][3];   // du[i][j] = d_i u_j
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        du[0][j] = dfd<P>(xl[j], c[j], xh[j], x, N, P(0), P(0), false);
+        du[1][j] = dfd<P>(yl[j], c[j], yh[j], y, N, P(0), P(0), false);
+        du[2][j] = dfd<P>(lo[j], c[j], hi[j], z, N, P(0), P(0), false);
+    }
+    const P dT[3] = {dfd<P>(xl[3], c[3], xh[3], x, N, Th, Tc, iso != 0),
+                     dfd<P>(yl[3], c[3], yh[3], y, N, Th, Tc, true),
+                     dfd<P>(lo[3], c[3], hi[3], z, N, Th, Tc, iso != 2)};
+    P eu = P(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const P sij = du[i][j] + du[j][i];
+            eu += sij * sij;
+        }
+    const P u = c[0], vv = c[1], w = c[2], Tn = c[3];
+    const P dr = cur.d;
+    const P div = du[0][0] + du[1][1] + du[2][2];
+    v[LBM_RAW_U2] += static_cast<double>(u * u + vv * vv + w * w);
+    v[LBM_RAW_W2] += static_cast<double>(w * w);
+    v[LBM_RAW_WT] += static_cast<double>(w * Tn);
+    v[LBM_RAW_UT] += static_cast<double>(u * Tn);
+    v[LBM_RAW_EPS_U] += static_cast<double>(P(0.5) * nu * eu);
+    v[LBM_RAW_EPS_T] += static_cast<double>(kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]));
+    v[LBM_RAW_DRHO2] += static_cast<double>(dr * dr);
+    v[LBM_RAW_T] += static_cast<double>(Tn);
+    v[LBM_RAW_DRHO] += static_cast<double>(dr);
+    v[LBM_RAW_DIV2] += static_cast<double>(div * div);
+    const int k = iso == 0 ? x : z;
+    if (k == 0 || k == N - 1) {
+        const bool hot = k == 0;
+        const P T_in = iso == 0 ? (hot ? xh[3] : xl[3]) : (hot ? hi[3] : lo[3]);
+        double fh = 0.0, fc = 0.0;
+        if (wall) {
+            if constexpr (CELL == LBM_SIDE_HEATED) {
+                fh = cur.wh;
+                fc = cur.wc;
+            } else {
+                fh = wall[x + static_cast<uint64_t>(N) * y];
+                fc = wall[N2 + x + static_cast<uint64_t>(N) * y];
+            }
+        }
+        // both walls' sums take a select: a sum chosen by a run-time index
+        // would move the sums to scratch memory
+        const P gh = -(P(-8) * Th + P(9) * Tn - T_in) * P(1.0 / 3.0);
+        const P gc = (P(8) * Tc - P(9) * Tn + T_in) * P(1.0 / 3.0);
+        v[LBM_RAW_FLUX_HOT] += hot ? fh : 0.0;
+        v[LBM_RAW_GRAD_HOT] += hot ? static_cast<double>(gh) : 0.0;
+        v[LBM_RAW_FLUX_COLD] += hot ? 0.0 : fc;
+        v[LBM_RAW_GRAD_COLD] += hot ? 0.0 : static_cast<double>(gc);
+    }
+}
+
 // Observable partial sums from the observation planes [rho - 1, u, v, w, T]
 // (type P; the differences and products are formed in P, each node's terms
 // added to FP64 sums) and the wall flux (NULL before the first step).  A
@@ -806,10 +950,13 @@ constexpr int kObsTile = 4 * 62;
 // ZC planes: the values at z - 1, z and z + 1 stay in registers, the
 // neighbours r +- 1 come from the neighbouring lanes (each wave's outer lanes
 // hold them), r +- N from the lines the block and its neighbours load at the
-// same time, so each plane value comes from HBM about once.  Logical block
-// lb = chunk * ntile + tile; every block writes one row of partials.  At
-// 257^3 in FP32: 206 us (from 618 us with a lane per node, edge loads and FP64
-// differences; 665 us for the earlier pass over FP64 planes).
+// same time, so each plane value comes from HBM about once.  Three plane
+// buffers rotate through the march, the loads of plane z + 2 issued before
+// plane z is worked on, and no buffer with loads in flight is ever copied.
+// Logical block lb = chunk * ntile + tile; every block writes one row of
+// partials.  At 257^3 in FP32: 215 us with one plane in flight and loads
+// under branches; 618 us with a lane per node, edge loads and FP64
+// differences; 665 us for the earlier pass over FP64 planes.
 template <int CELL, class P, int ZC = kObsZ>
 __global__ __launch_bounds__(kRedBlock) void k_observe(int N, uint32_t ntile, ObsArgs a,
                                                        const P *__restrict__ pl,
@@ -822,104 +969,49 @@ __global__ __launch_bounds__(kRedBlock) void k_observe(int N, uint32_t ntile, Ob
     // the first and last lane of each wave only carry the values of the
     // neighbours r - 1 and r + 1 of the 62 lanes between them
     const int ri = static_cast<int>(tile) * kObsTile + wave * 62 + lane - 1;
-    const bool has = ri >= 0 && ri < N2;                  // a node whose values this lane loads
-    const bool live = has && lane >= 1 && lane <= 62;     // ... and whose terms it adds
+    const bool live = ri >= 0 && ri < N2 && lane >= 1 && lane <= 62;   // adds its node's terms
+    const int rc = min(max(ri, 0), N2 - 1);                            // in-bounds node to load
+    const int y = rc / N, x = rc - y * N;
+    const int ryl = y > 0 ? rc - N : rc, ryh = y < N - 1 ? rc + N : rc;
     double v[LBM_NRAW];
 #pragma unroll
     for (int k = 0; k < LBM_NRAW; ++k) v[k] = 0.0;
     const uint64_t V = static_cast<uint64_t>(N2) * N;
-    const P *D = pl, *F[4] = {pl + V, pl + 2 * V, pl + 3 * V, pl + 4 * V};   // u, v, w, T
-    const int y = has ? ri / N : 0, x = has ? ri - y * N : 0;
+    const P *const F[4] = {pl + V, pl + 2 * V, pl + 3 * V, pl + 4 * V};   // u, v, w, T
+    // the observation planes hold 5 N^3 values of at least 4 bytes, more than
+    // the 2 N^2 doubles the wall fluxes take
+    const double *wsrc = wall ? wall : reinterpret_cast<const double *>(pl);
     const int z0 = static_cast<int>(chunk) * ZC, z1 = min(N, z0 + ZC);
-    constexpr int iso = CELL == LBM_SIDE_HEATED ? 0 : 2;
     const int mid_lo = (N - 1) / 2, mid_hi = N / 2;
     const double wm = (y == mid_lo || y == mid_hi) ? (mid_lo == mid_hi ? 1.0 : 0.5) : 0.0;
-    const P nu = static_cast<P>(a.nu), kappa = static_cast<P>(a.kappa);
-    const P Th = static_cast<P>(a.T_hot), Tc = static_cast<P>(a.T_cold);
-    // (u, v, w, T) at z - 1, z, z + 1 and at y -+ 1 of plane z; the loads for
-    // plane z + 1 are issued before plane z is worked on, so their latency
-    // overlaps the arithmetic
-    P lo[4], c[4], hi[4], yl[4], yh[4];
+    ObsPlane<CELL, P> A, B, C;
+    P lo[4];
     {
-        const P *p0[4];
+        const uint64_t zl = static_cast<uint64_t>(max(z0 - 1, 0)) * N2;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            p0[q] = F[q] + static_cast<uint64_t>(z0) * N2;
-            c[q] = has ? p0[q][ri] : P(0);
-            lo[q] = has && z0 > 0 ? p0[q][ri - N2] : P(0);
-            hi[q] = has && z0 + 1 < N ? p0[q][ri + N2] : P(0);
-            yl[q] = live && y > 0 ? p0[q][ri - N] : P(0);
-            yh[q] = live && y < N - 1 ? p0[q][ri + N] : P(0);
-        }
+        for (int q = 0; q < 4; ++q) lo[q] = F[q][zl + rc];
     }
+    obs_load(A, F, pl, wsrc, z0, N, N2, rc, ryl, ryh);
+    obs_load(B, F, pl, wsrc, min(z0 + 1, N - 1), N, N2, rc, ryl, ryh);
+    // planes z, z + 1 and z + 2 rotate through A, B and C
+    int z = z0;
 #pragma unroll 1
-    for (int z = z0; z < z1; ++z) {
-        P nhi[4], nyl[4], nyh[4], xl[4], xh[4];
-        const bool more = z + 1 < z1;
+    while (true) {
+        obs_load(C, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, ryl, ryh);
+        obs_terms(v, lo, A, B.c, x, y, z, N, N2, live, wall, a);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const P *p1 = F[q] + static_cast<uint64_t>(z + 1) * N2;
-            nhi[q] = more && has && z + 2 < N ? p1[ri + N2] : P(0);
-            nyl[q] = more && live && y > 0 ? p1[ri - N] : P(0);
-            nyh[q] = more && live && y < N - 1 ? p1[ri + N] : P(0);
-            // r - 1 and r + 1 are the neighbouring lanes' own values
-            xl[q] = __shfl_up(c[q], 1, 64);
-            xh[q] = __shfl_down(c[q], 1, 64);
-        }
-        if (live) {
-            P du[3][3];   // du[i][j] = d_i u_j
+        for (int q = 0; q < 4; ++q) lo[q] = A.c[q];
+        if (++z >= z1) break;
+        obs_load(A, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, ryl, ryh);
+        obs_terms(v, lo, B, C.c, x, y, z, N, N2, live, wall, a);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                du[0][j] = dfd<P>(xl[j], c[j], xh[j], x, N, P(0), P(0), false);
-                du[1][j] = dfd<P>(yl[j], c[j], yh[j], y, N, P(0), P(0), false);
-                du[2][j] = dfd<P>(lo[j], c[j], hi[j], z, N, P(0), P(0), false);
-            }
-            const P dT[3] = {dfd<P>(xl[3], c[3], xh[3], x, N, Th, Tc, iso != 0),
-                             dfd<P>(yl[3], c[3], yh[3], y, N, Th, Tc, true),
-                             dfd<P>(lo[3], c[3], hi[3], z, N, Th, Tc, iso != 2)};
-            P eu = P(0);
+        for (int q = 0; q < 4; ++q) lo[q] = B.c[q];
+        if (++z >= z1) break;
+        obs_load(B, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, ryl, ryh);
+        obs_terms(v, lo, C, A.c, x, y, z, N, N2, live, wall, a);
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const P sij = du[i][j] + du[j][i];
-                    eu += sij * sij;
-                }
-            const P u = c[0], vv = c[1], w = c[2], Tn = c[3];
-            const P dr = (D + static_cast<uint64_t>(z) * N2)[ri];
-            const P div = du[0][0] + du[1][1] + du[2][2];
-            v[LBM_RAW_U2] += static_cast<double>(u * u + vv * vv + w * w);
-            v[LBM_RAW_W2] += static_cast<double>(w * w);
-            v[LBM_RAW_WT] += static_cast<double>(w * Tn);
-            v[LBM_RAW_UT] += static_cast<double>(u * Tn);
-            v[LBM_RAW_EPS_U] += static_cast<double>(P(0.5) * nu * eu);
-            v[LBM_RAW_EPS_T] += static_cast<double>(kappa * (dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]));
-            v[LBM_RAW_DRHO2] += static_cast<double>(dr * dr);
-            v[LBM_RAW_T] += static_cast<double>(Tn);
-            v[LBM_RAW_DRHO] += static_cast<double>(dr);
-            v[LBM_RAW_DIV2] += static_cast<double>(div * div);
-            const int k = iso == 0 ? x : z;
-            if (k == 0 || k == N - 1) {
-                const P T_in = iso == 0 ? (k == 0 ? xh[3] : xl[3]) : (k == 0 ? hi[3] : lo[3]);
-                const uint64_t w2 = CELL == LBM_SIDE_HEATED ? y + static_cast<uint64_t>(N) * z
-                                                            : x + static_cast<uint64_t>(N) * y;
-                if (k == 0) {
-                    v[LBM_RAW_FLUX_HOT] += wall ? wall[w2] : 0.0;
-                    v[LBM_RAW_GRAD_HOT] += static_cast<double>(-(P(-8) * Th + P(9) * Tn - T_in) * P(1.0 / 3.0));
-                } else {
-                    v[LBM_RAW_FLUX_COLD] += wall ? wall[N2 + w2] : 0.0;
-                    v[LBM_RAW_GRAD_COLD] += static_cast<double>((P(8) * Tc - P(9) * Tn + T_in) * P(1.0 / 3.0));
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            lo[q] = c[q];
-            c[q] = hi[q];
-            hi[q] = nhi[q];
-            yl[q] = nyl[q];
-            yh[q] = nyh[q];
-        }
+        for (int q = 0; q < 4; ++q) lo[q] = C.c[q];
+        if (++z >= z1) break;
     }
     // the mid-line weight depends on y only, which a thread keeps (0, 1/2 or
     // 1: the scaling is exact)
