@@ -840,7 +840,7 @@ struct ObsPlane {
     double wh, wc;
 };
 
-// Loads of plane zc for in-plane node rc (rows ryl, ryh for y -+ 1), every one
+// Loads of plane zc for in-plane node rc = x + N y (rows ryl, ryh for y -+ 1), every one
 // issued by every lane at an address clamped into the arrays: a load under a
 // branch would make the compiler wait for all loads in flight before its value
 // is used, which serialises the planes.  Values at clamped addresses are not
@@ -849,7 +849,7 @@ struct ObsPlane {
 template <int CELL, class P>
 __device__ __forceinline__ void obs_load(ObsPlane<CELL, P> &o, const P *const (&F)[4],
                                          const P *D, const double *wsrc, int zc, int N, int N2,
-                                         int rc, int ryl, int ryh) {
+                                         int rc, int y, int ryl, int ryh) {
     const uint64_t zo = static_cast<uint64_t>(zc) * N2;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -859,7 +859,7 @@ __device__ __forceinline__ void obs_load(ObsPlane<CELL, P> &o, const P *const (&
     }
     o.d = D[zo + rc];
     if constexpr (CELL == LBM_SIDE_HEATED) {
-        const uint64_t w = rc / N + static_cast<uint64_t>(N) * zc;   // y + N z
+        const uint64_t w = y + static_cast<uint64_t>(N) * zc;
         o.wh = wsrc[w];
         o.wc = wsrc[static_cast<uint64_t>(N2) + w];
     }
@@ -943,6 +943,14 @@ __device__ __forceinline__ void obs_terms(double (&v)[LBM_NRAW], const P (&lo)[4
     }
 }
 
+// Waves per SIMD the observable reduction is compiled for: 4 (128 VGPRs) for
+// the Rayleigh-Benard cell with FP32 planes, 3-8% faster than the 3 waves its
+// registers would otherwise allow; otherwise whatever the registers allow
+// (held to 128 VGPRs the side-heated cell spills 16 bytes a lane, which
+// costs more than the extra wave gains, and FP64 planes spill heavily).
+template <int CELL, class P>
+constexpr int kObsWaves = (sizeof(P) == 4 && CELL == LBM_RAYLEIGH_BENARD) ? 4 : 1;
+
 // Observable partial sums from the observation planes [rho - 1, u, v, w, T]
 // (type P; the differences and products are formed in P, each node's terms
 // added to FP64 sums) and the wall flux (NULL before the first step).  A
@@ -954,11 +962,12 @@ __device__ __forceinline__ void obs_terms(double (&v)[LBM_NRAW], const P (&lo)[4
 // buffers rotate through the march, the loads of plane z + 2 issued before
 // plane z is worked on, and no buffer with loads in flight is ever copied.
 // Logical block lb = chunk * ntile + tile; every block writes one row of
-// partials.  At 257^3 in FP32: 215 us with one plane in flight and loads
-// under branches; 618 us with a lane per node, edge loads and FP64
-// differences; 665 us for the earlier pass over FP64 planes.
+// partials.  At 257^3 in FP32: 108-121 us (195 us with one plane in flight
+// and its loads under branches; 618 us with a lane per node, edge loads and
+// FP64 differences; 665 us for the earlier pass over FP64 planes).
 template <int CELL, class P, int ZC = kObsZ>
-__global__ __launch_bounds__(kRedBlock) void k_observe(int N, uint32_t ntile, ObsArgs a,
+__global__ __launch_bounds__(kRedBlock) __attribute__((amdgpu_waves_per_eu(kObsWaves<CELL, P>)))
+void k_observe(int N, uint32_t ntile, ObsArgs a,
                                                        const P *__restrict__ pl,
                                                        const double *__restrict__ wall,
                                                        double *__restrict__ part) {
@@ -991,23 +1000,23 @@ __global__ __launch_bounds__(kRedBlock) void k_observe(int N, uint32_t ntile, Ob
 #pragma unroll
         for (int q = 0; q < 4; ++q) lo[q] = F[q][zl + rc];
     }
-    obs_load(A, F, pl, wsrc, z0, N, N2, rc, ryl, ryh);
-    obs_load(B, F, pl, wsrc, min(z0 + 1, N - 1), N, N2, rc, ryl, ryh);
+    obs_load(A, F, pl, wsrc, z0, N, N2, rc, y, ryl, ryh);
+    obs_load(B, F, pl, wsrc, min(z0 + 1, N - 1), N, N2, rc, y, ryl, ryh);
     // planes z, z + 1 and z + 2 rotate through A, B and C
     int z = z0;
 #pragma unroll 1
     while (true) {
-        obs_load(C, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, ryl, ryh);
+        obs_load(C, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, y, ryl, ryh);
         obs_terms(v, lo, A, B.c, x, y, z, N, N2, live, wall, a);
 #pragma unroll
         for (int q = 0; q < 4; ++q) lo[q] = A.c[q];
         if (++z >= z1) break;
-        obs_load(A, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, ryl, ryh);
+        obs_load(A, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, y, ryl, ryh);
         obs_terms(v, lo, B, C.c, x, y, z, N, N2, live, wall, a);
 #pragma unroll
         for (int q = 0; q < 4; ++q) lo[q] = B.c[q];
         if (++z >= z1) break;
-        obs_load(B, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, ryl, ryh);
+        obs_load(B, F, pl, wsrc, min(z + 2, N - 1), N, N2, rc, y, ryl, ryh);
         obs_terms(v, lo, C, A.c, x, y, z, N, N2, live, wall, a);
 #pragma unroll
         for (int q = 0; q < 4; ++q) lo[q] = C.c[q];

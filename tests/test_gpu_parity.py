@@ -308,6 +308,22 @@ def test_fields_and_observables(cell, storage, N):
     assert abs(eT - nd["eps_T"]) <= 1e-4 * nd["eps_T"]
 
 
+@pytest.mark.parametrize("cell", [0, 1])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_observables_before_the_first_step(cell, storage):
+    """Before any step there is no wall link flux yet: zero on both walls, as
+    in the oracle; every other sum comes from the fields just set (the
+    reduction reads no flux array then)."""
+    pr = Pair(19, 1e5, 0.71, cell, storage, U=0.1)
+    pr.init_rich()
+    tol = 1e-11 if storage == "fp64" else 2e-5
+    rg = np.asarray(B.lbm_observables_raw(pr.h))
+    ro = pr.o.observables_raw()
+    assert (rg[0:4] == 0).all() and (ro[0:4] == 0).all()
+    assert np.abs(rg[4:8]).max() > 0
+    _raw_close(rg, ro, tol * (10 if storage == "fp32" else 1), _raw_floor(pr.p))
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_residual_against_oracle(storage):
     pr = Pair(17, 1e5, 0.71, 0, storage, U=0.1)
