@@ -76,9 +76,41 @@ def batch_means(params, raws, batches):
     return [_summary(params, _mean_raw(raws[i * g:(i + 1) * g])) for i in range(batches)]
 
 
+def averaging_plan(avg_steps, sub, sample_every, batches=None, prefix_steps=None):
+    """Steps per averaging sub-block (a whole number of sample intervals) and
+    the number of leading sub-blocks the prefix covers (None without one).
+    Raises ValueError, before anything runs, when `batches` does not divide
+    `sub` or the prefix is not 2..sub whole sub-blocks."""
+    per = max(sample_every, (avg_steps // sub) // sample_every * sample_every)
+    if batches is not None and (batches <= 0 or sub % batches):
+        raise ValueError(f"{sub} sub-blocks do not split into {batches} batches")
+    k = None
+    if prefix_steps:
+        k = prefix_steps // per
+        if k < 2 or k * per != prefix_steps or k > sub:
+            raise ValueError(f"prefix of {prefix_steps} steps is not 2..{sub} sub-blocks of {per}")
+    return per, k
+
+
+def summarize_averages(params, raws, batches=None, k_prefix=None):
+    """Means and standard errors of the averaging sub-blocks' raw sums: the
+    mean from the pooled sums, the errors over `batches` runs of consecutive
+    sub-blocks (or over the sub-blocks), and the same for the first
+    `k_prefix` sub-blocks (errors over its sub-blocks)."""
+    subs = [_summary(params, r) for r in raws]
+    mean = _summary(params, _mean_raw(raws))
+    se = standard_errors(batch_means(params, raws, batches) if batches else subs, KEYS)
+    prefix = None
+    if k_prefix:
+        prefix = {"mean": _summary(params, _mean_raw(raws[:k_prefix])),
+                  "stderr": standard_errors(subs[:k_prefix], KEYS)}
+    return mean, se, prefix
+
+
 def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, settle=0.01,
              max_transient_tf=400.0, avg_steps=100_000, sub=10, sample_every=100, log=print,
              batches=None, prefix_steps=None):
+    per, k_prefix = averaging_plan(avg_steps, sub, sample_every, batches, prefix_steps)
     opts = B.lbm_default_opts(sample_every=sample_every)
     h = B.lbm_create(N, Ra, Pr, "rayleigh_benard", storage, opts)
     p = B.lbm_get_params(h)
@@ -107,7 +139,6 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
             log(f"# {storage}: block means still moving after {max_transient_tf:.0f} t_f")
             break
     transient = steps
-    per = max(sample_every, (avg_steps // sub) // sample_every * sample_every)
     subs, raws = [], []
     ta = time.perf_counter()
     for i in range(sub):
@@ -120,8 +151,7 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
             f"Re_rms {subs[-1]['Re_rms']:.2f}  {time.perf_counter() - t0:.0f} s")
     torch.cuda.synchronize()
     wall_avg = time.perf_counter() - ta
-    mean = _summary(p, _mean_raw(raws))
-    se = standard_errors(batch_means(p, raws, batches) if batches else subs, KEYS)
+    mean, se, prefix = summarize_averages(p, raws, batches, k_prefix)
     out = {"N": N, "Ra": Ra, "Pr": Pr, "storage": storage, "seed": seed,
            "steps_per_tf": tf, "transient_steps": transient, "transient_block_Nu_vol": trans,
            "settled": settled,
@@ -130,14 +160,9 @@ def run_case(N, Ra, Pr, storage, seed, min_transient_tf=100.0, block_tf=20.0, se
            "mean": mean, "stderr": se,
            "MLUPS_averaging": N ** 3 * per * sub / wall_avg / 1e6,
            "wall_s": time.perf_counter() - t0}
-    if prefix_steps:
-        k = prefix_steps // per
-        if k < 2 or k * per != prefix_steps or k > sub:
-            raise ValueError(f"prefix of {prefix_steps} steps is not 2..{sub} sub-blocks of {per}")
-        out["prefix"] = {"avg_steps": k * per, "avg_tf": k * per / tf,
-                         "mean": _summary(p, _mean_raw(raws[:k])),
-                         "stderr": standard_errors(subs[:k], KEYS),
-                         "stderr_over": f"{k} sub-blocks"}
+    if prefix:
+        out["prefix"] = {"avg_steps": k_prefix * per, "avg_tf": k_prefix * per / tf, **prefix,
+                         "stderr_over": f"{k_prefix} sub-blocks"}
     ref = PAPER.get((Ra, Pr))
     if ref:
         out["paper"] = dict(zip(KEYS[:6], ref))

@@ -68,3 +68,37 @@ def test_rayleigh_benard_batch_means_summarise_the_pooled_sums():
     assert all(abs(pairs[1][k] - want[k]) <= 1e-14 * abs(want[k]) for k in want)
     with pytest.raises(ValueError):
         batch_means(p, raws, 4)
+
+
+def test_rayleigh_benard_averaging_plan_refuses_bad_splits_before_running():
+    from paper_1903_08882_amd.rb import averaging_plan
+    assert averaging_plan(300_000, 30, 100, 10, 100_000) == (10_000, 10)
+    assert averaging_plan(100_000, 10, 100) == (10_000, None)
+    # sub-blocks are whole sample intervals
+    assert averaging_plan(100_050, 10, 100)[0] == 10_000
+    for bad in [dict(batches=7), dict(batches=0), dict(prefix_steps=10_000),
+                dict(prefix_steps=105_000), dict(prefix_steps=400_000)]:
+        with pytest.raises(ValueError):
+            averaging_plan(300_000, 30, 100, **bad)
+
+
+def test_rayleigh_benard_summary_of_sub_blocks():
+    """The mean comes from the pooled sums; the prefix is the same summary of
+    the leading sub-blocks; with every sub-block equal the errors vanish."""
+    import numpy as np
+    from paper_1903_08882_amd import binding as B
+    from paper_1903_08882_amd.rb import KEYS, _summary, summarize_averages
+    p = B.lbm_derive_params(33, 1e6, 0.7, 1)
+    rng = np.random.default_rng(9)
+    raws = [list(rng.uniform(1e-3, 1e-2, B.NRAW)) for _ in range(6)]
+    mean, se, prefix = summarize_averages(p, raws, batches=3, k_prefix=2)
+    pooled = _summary(p, [sum(r[j] for r in raws) / 6 for j in range(B.NRAW)])
+    first2 = _summary(p, [(raws[0][j] + raws[1][j]) / 2 for j in range(B.NRAW)])
+    for k in KEYS:
+        assert abs(mean[k] - pooled[k]) <= 1e-14 * abs(pooled[k])
+        assert abs(prefix["mean"][k] - first2[k]) <= 1e-14 * abs(first2[k])
+        assert se[k] > 0 and prefix["stderr"][k] > 0
+    same = [raws[0]] * 4
+    _, se0, _ = summarize_averages(p, same, batches=2)
+    assert all(se0[k] == 0 for k in KEYS)
+    assert summarize_averages(p, raws)[2] is None
